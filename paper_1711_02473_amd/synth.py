@@ -1,0 +1,101 @@
+"""Seeded synthetic inputs (meshes, coefficients, DOF vectors).
+
+This module only draws random numbers and lays out mesh geometry; it holds
+none of the assembly arithmetic.  It is the one piece of code that both the
+GPU path's callers and the oracle's callers use, so that both see identical
+bytes.
+
+Recipe: ``numpy.random.default_rng([171102473, config_id, stream])`` with
+stream 0 = cell spacings, 1 = kappa, 2 = DOF vectors, 3 = batched-workload
+mesh sizes and degrees, 4 = geometric perturbations.  Spacings are
+U[0.5, 1.5], kappa U[0.5, 2] per quadrature point, DOF vectors N(0, 1).
+
+Meshes are conforming tensor grids of axis-aligned boxes: per-axis spacings
+drawn independently, vertex coordinates at their cumulative sums from 0.
+Cell (i, j, k) is number (i*ny + j)*nz + k; its reference vertex
+(v0, v1, v2) in {0,1}^3 is stored at index 4*v0 + 2*v1 + v2.
+"""
+import numpy as np
+
+SEED = 171102473
+
+
+def rng(config_id, stream):
+    return np.random.default_rng([SEED, int(config_id), int(stream)])
+
+
+def grid_vertices(xs, ys, zs):
+    """Per-cell vertex array [ncells][8][3] of the tensor grid with node coordinates xs, ys, zs."""
+    xs = np.asarray(xs, dtype=np.float64)
+    ys = np.asarray(ys, dtype=np.float64)
+    zs = np.asarray(zs, dtype=np.float64)
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    V = np.empty((nx, ny, nz, 8, 3), dtype=np.float64)
+    for v0 in (0, 1):
+        for v1 in (0, 1):
+            for v2 in (0, 1):
+                v = 4 * v0 + 2 * v1 + v2
+                V[:, :, :, v, 0] = xs[v0:nx + v0][:, None, None]
+                V[:, :, :, v, 1] = ys[v1:ny + v1][None, :, None]
+                V[:, :, :, v, 2] = zs[v2:nz + v2][None, None, :]
+    return V.reshape(nx * ny * nz, 8, 3)
+
+
+def box_spacings(nx, ny, nz, config_id):
+    g = rng(config_id, 0)
+    hx = g.uniform(0.5, 1.5, nx)
+    hy = g.uniform(0.5, 1.5, ny)
+    hz = g.uniform(0.5, 1.5, nz)
+    return hx, hy, hz
+
+
+def box_mesh(nx, ny, nz, config_id):
+    """Box cells with edge lengths U[0.5, 1.5]: vertices [nx*ny*nz][8][3]."""
+    hx, hy, hz = box_spacings(nx, ny, nz, config_id)
+    cum = lambda h: np.concatenate([[0.0], np.cumsum(h)])
+    return grid_vertices(cum(hx), cum(hy), cum(hz))
+
+
+def kappa(ncells, nq, config_id, dtype=np.float64):
+    """Coefficient per quadrature point, U[0.5, 2], [ncells][nq]."""
+    return rng(config_id, 1).uniform(0.5, 2.0, (ncells, nq)).astype(dtype)
+
+
+def dof_vector(ncells, ndof, config_id, dtype=np.float64):
+    """Cell-major local DOF vector, N(0, 1), [ncells][ndof]."""
+    return rng(config_id, 2).standard_normal((ncells, ndof)).astype(dtype)
+
+
+def batched_workload(nmeshes=2048, config_id=5, nmin=4, nmax=16, pmin=2, pmax=8):
+    """Sizes and degrees of the batched mixed workload: list of (n_m, p_m),
+    n_m uniform in {nmin..nmax} (n_m^3 cells), p_m uniform in {pmin..pmax}."""
+    g = rng(config_id, 3)
+    ns = g.integers(nmin, nmax + 1, nmeshes)
+    ps = g.integers(pmin, pmax + 1, nmeshes)
+    return [(int(a), int(b)) for a, b in zip(ns, ps)]
+
+
+def affine_cells(ncells, config_id, shear=0.3):
+    """Parallelepiped cells x = x0 + J xi with J = diag(U[0.5,1.5]) + U[-shear, shear]
+    off the diagonal (det J > 0 for shear <= 0.3)."""
+    g = rng(config_id, 4)
+    x0 = g.uniform(-1.0, 1.0, (ncells, 3))
+    J = g.uniform(-shear, shear, (ncells, 3, 3))
+    d = g.uniform(0.5, 1.5, (ncells, 3))
+    for a in range(3):
+        J[:, a, a] = d[:, a]
+    V = np.empty((ncells, 8, 3))
+    for v0 in (0, 1):
+        for v1 in (0, 1):
+            for v2 in (0, 1):
+                xi = np.array([v0, v1, v2], dtype=np.float64)
+                V[:, 4 * v0 + 2 * v1 + v2, :] = x0 + J @ xi
+    return V
+
+
+def trilinear_cells(ncells, config_id, amp=0.15):
+    """Unit-ish boxes with every vertex moved by U[-amp, amp] per coordinate
+    (a genuinely trilinear, non-affine map; det J > 0 for amp <= 0.15)."""
+    g = rng(config_id, 4)
+    V = box_mesh(1, 1, 1, config_id).repeat(ncells, axis=0)
+    return V + g.uniform(-amp, amp, V.shape)
