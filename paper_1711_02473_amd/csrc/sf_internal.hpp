@@ -1,0 +1,86 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sf.h"
+
+namespace sf {
+
+constexpr int kMaxRule = 32;
+
+int rule_1d(int kind, int m, double *x, double *w);
+int lagrange_table(int nn, const double *nodes, int np, const double *pts, double *B, double *D);
+
+// Layout of the per-(family, degree, nq1) table block, identical for every
+// storage type.  Space 0 has n0 functions (Q: GLL nodes; dQ: GL nodes; NCF /
+// NCE: the P_k factor on GLL_{k+1}); space 1 has n1 functions (NCF / NCE: the
+// dP_{k-1} factor on GL_k; 0 for scalar families).
+//   B0[nq][n0]  values of space 0 at the GL points
+//   D0[nq][n0]  derivatives of space 0
+//   B1[nq][n1], D1[nq][n1]
+//   Dh[nq][nq]  collocation derivative of the Lagrange basis on the GL points
+//   w[nq]       GL weights on [0,1]
+struct TabLayout {
+    int n0, n1, nq;
+    __host__ __device__ constexpr TabLayout(int a, int b, int c) : n0(a), n1(b), nq(c) {}
+    __host__ __device__ constexpr int B0() const { return 0; }
+    __host__ __device__ constexpr int D0() const { return nq * n0; }
+    __host__ __device__ constexpr int B1() const { return 2 * nq * n0; }
+    __host__ __device__ constexpr int D1() const { return 2 * nq * n0 + nq * n1; }
+    __host__ __device__ constexpr int Dh() const { return 2 * nq * (n0 + n1); }
+    __host__ __device__ constexpr int W() const { return 2 * nq * (n0 + n1) + nq * nq; }
+    __host__ __device__ constexpr int size() const { return W() + nq; }
+};
+
+// Tables split into three bf16 terms (hi, mid, lo) and single fp16 / bf16
+// copies live after the fp64 and fp32 blocks; see mixed.hip.
+struct TableSet {
+    int len = 0;
+    double *d64 = nullptr;
+    float *f32 = nullptr;
+    void *mixed = nullptr; // low-precision tables (layout owned by mixed.hip)
+};
+
+struct LaunchArgs {
+    int family, degree, form, nq, n0, n1, precision, io;
+    double alpha, beta;
+    int64_t ncells;
+    const double *vert;
+    const void *kappa;
+    const void *u;
+    void *y;
+    void *A;
+    const double *tab64;
+    const float *tab32;
+    const void *tabmix;
+    int *err;
+    hipStream_t stream;
+    int variant;
+};
+
+// kernel launchers: return SF_OK, SF_ERR_UNSUPPORTED or SF_ERR_HIP
+int launch_action_q(const LaunchArgs &a);
+int launch_matrix_q(const LaunchArgs &a);
+int launch_action_vec(const LaunchArgs &a);
+int launch_matrix_vec(const LaunchArgs &a);
+int launch_action_mixed(const LaunchArgs &a);
+int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);
+
+// number of tile variants compiled for an op (autotuner search space)
+int action_variants(const LaunchArgs &a);
+
+} // namespace sf
+
+struct sf_context {
+    int device = 0;
+    int *d_err = nullptr;
+    std::map<std::tuple<int, int, int>, sf::TableSet> tables;
+    std::map<std::string, int> tuned;
+};
