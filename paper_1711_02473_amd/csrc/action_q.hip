@@ -35,9 +35,12 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
     constexpr int NBUF = (FORM == SF_LAPLACE) ? 3 : 2;
     constexpr TabLayout TL(N, 0, NQ);
     constexpr int N3 = N * N * N, NQ3 = NQ * NQ * NQ;
-    const T *__restrict__ Bt = tab + TL.B0();
-    const T *__restrict__ Dh = tab + TL.Dh();
-    const T *__restrict__ W = tab + TL.W();
+    const T *const Bt = tab + TL.B0();   // B [nq][n]
+    const T *const BtT = tab + TL.B0T(); // B^T [n][nq]
+    const T *const Dh = tab + TL.Dh();
+    const T *const DhT = tab + TL.DhT();
+    const T *const tW = tab + TL.W();
+#define W fresh(tW)
 
     constexpr bool NEED_LDS = !(COLL && FORM == SF_MASS);
     __shared__ T lds[NEED_LDS ? NBUF * C * CS : 1];
@@ -130,7 +133,7 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
                 const T w12 = T(sP[c][0]) * W[q1] * W[q2];
 #pragma unroll
                 for (int q3 = 0; q3 < NQ; ++q3) ut[q3] *= w12 * W[q3] * k[q3];
-                mtv<NQ, N>(Bt, ut, t);
+                mtv<NQ, N>(BtT, ut, t);
                 st_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, t);
             });
             __syncthreads();
@@ -180,7 +183,7 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
                     gy[q1] = om * (p01 * a + p11 * b + p12 * d);
                     gz[q1] = om * (p02 * a + p12 * b + p22 * d);
                 }
-                mtv<NQ, NQ>(Dh, gx, ut);
+                mtv<NQ, NQ>(DhT, gx, ut);
                 st_pencil<0, NQ, S1, S2>(L0 + c * CS, q2, q3, ut);
                 st_pencil<0, NQ, S1, S2>(L2 + c * CS, q2, q3, gy);
                 st_pencil<0, NQ, S1, S2>(L1 + c * CS, q2, q3, gz);
@@ -191,7 +194,7 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
                 T wv[NQ], vy[NQ];
                 ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, wv);
                 ld_pencil<1, NQ, S1, S2>(L2 + c * CS, q1, q3, vy);
-                mtv_acc<NQ, NQ>(Dh, vy, wv);
+                mtv_acc<NQ, NQ>(DhT, vy, wv);
                 st_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, wv);
             });
             __syncthreads();
@@ -200,12 +203,12 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
                 T wv[NQ], vz[NQ];
                 ld_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, wv);
                 ld_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, vz);
-                mtv_acc<NQ, NQ>(Dh, vz, wv);
+                mtv_acc<NQ, NQ>(DhT, vz, wv);
                 if constexpr (COLL) {
                     st_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, wv);
                 } else {
                     T t[N];
-                    mtv<NQ, N>(Bt, wv, t);
+                    mtv<NQ, N>(BtT, wv, t);
                     st_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, t);
                 }
             });
@@ -217,7 +220,7 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
             pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
                 T in[NQ], out[N];
                 ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, i3, in);
-                mtv<NQ, N>(Bt, in, out);
+                mtv<NQ, N>(BtT, in, out);
                 st_pencil<1, N, S1, S2>(L0 + c * CS, q1, i3, out);
             });
             __syncthreads();
@@ -232,13 +235,15 @@ __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, cons
 #pragma unroll
                 for (int i1 = 0; i1 < N; ++i1) out[i1] = in[i1];
             } else {
-                mtv<NQ, N>(Bt, in, out);
+                mtv<NQ, N>(BtT, in, out);
             }
 #pragma unroll
             for (int i1 = 0; i1 < N; ++i1) y[gc * N3 + (i1 * N + i2) * N + i3] = IO(out[i1]);
         });
     }
 }
+
+#undef W
 
 namespace {
 

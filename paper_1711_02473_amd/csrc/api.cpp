@@ -79,6 +79,15 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
     std::vector<double> tmpB(size_t(d.nq1) * d.nq1);
     lagrange_table(d.nq1, xq.data(), d.nq1, xq.data(), tmpB.data(), h.data() + L.Dh());
     std::copy(wq.begin(), wq.end(), h.begin() + L.W());
+    auto transpose = [&](int src, int dst, int rows, int cols) {
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) h[dst + size_t(c) * rows + r] = h[src + size_t(r) * cols + c];
+    };
+    transpose(L.B0(), L.B0T(), d.nq1, d.n0);
+    transpose(L.D0(), L.D0T(), d.nq1, d.n0);
+    transpose(L.B1(), L.B1T(), d.nq1, d.n1);
+    transpose(L.D1(), L.D1T(), d.nq1, d.n1);
+    transpose(L.Dh(), L.DhT(), d.nq1, d.nq1);
 
     TableSet ts;
     ts.len = L.size();

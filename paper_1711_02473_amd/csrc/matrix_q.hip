@@ -36,23 +36,23 @@ __global__ void __launch_bounds__(NT) matrix_q_kernel(const int64_t ncells, cons
     constexpr int NR = NS;                            // final-stage types: r=0 (D on axis 0 / mass: B), r=1 (B)
     constexpr int T1SZ = NQ2 * N2;
     constexpr int T2SZ = NQ * N2;
-    const double *__restrict__ Bt = tab + TL.B0();
-    const double *__restrict__ Dt = tab + TL.D0();
-    const double *__restrict__ W = tab + TL.W();
+    const double *const BT = tab + TL.B0T(); // B^T [n][nq]: row i = column i of B
+    const double *const DT = tab + TL.D0T();
 
     __shared__ double sT1[NS * C * T1SZ];
     __shared__ double sT2[2 * NR * C * T2SZ];
-    __shared__ double sB[NQ * N], sD[NQ * N], sW[NQ];
+    __shared__ double sBw[NQ * N], sDw[NQ * N], sW[NQ]; // w_q B[q][j], w_q D[q][j]
     __shared__ double sCoef[C][3];
 
     const int64_t cell0 = int64_t(blockIdx.x) * C;
     const bool has_kappa = kappa != nullptr;
 
-    for (int t = threadIdx.x; t < NQ * N; t += NT) {
-        sB[t] = Bt[t];
-        sD[t] = Dt[t];
+    for (int t = threadIdx.x; t < NQ * N; t += NT) { // lane-varying reads: plain vector loads
+        const double w = tab[TL.W() + t / N];
+        sBw[t] = w * tab[TL.B0() + t];
+        sDw[t] = w * tab[TL.D0() + t];
     }
-    if (threadIdx.x < NQ) sW[threadIdx.x] = W[threadIdx.x];
+    if (threadIdx.x < NQ) sW[threadIdx.x] = tab[TL.W() + threadIdx.x];
     if (threadIdx.x < C) {
         const int64_t gc = cell0 + threadIdx.x;
         double cf[3] = {0, 0, 0};
@@ -88,20 +88,17 @@ __global__ void __launch_bounds__(NT) matrix_q_kernel(const int64_t ncells, cons
             kw[q2] = sW[q2] * ((has_kappa && gc < ncells) ? to_d(kappa[gc * NQ3 + q01 * NQ + q2]) : 1.0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double *X = s == 0 ? Bt : Dt;
+            const double *XT = s == 0 ? BT : DT;
             double *dst = sT1 + (s * C + c) * T1SZ + q01 * N2;
 #pragma unroll
             for (int j2 = 0; j2 < N; ++j2) {
-                double tmp[NQ];
+                double tmp[NQ], col[N];
+                cptr<double> xr = fresh(XT + j2 * NQ);
 #pragma unroll
-                for (int q2 = 0; q2 < NQ; ++q2) tmp[q2] = X[q2 * N + j2] * kw[q2];
+                for (int q2 = 0; q2 < NQ; ++q2) tmp[q2] = xr[q2] * kw[q2];
+                mv<N, NQ>(XT, tmp, col); // col[i2] = sum_q2 X[q2][i2] tmp[q2]
 #pragma unroll
-                for (int i2 = 0; i2 < N; ++i2) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int q2 = 0; q2 < NQ; ++q2) acc = __builtin_fma(X[q2 * N + i2], tmp[q2], acc);
-                    dst[i2 * N + j2] = acc;
-                }
+                for (int i2 = 0; i2 < N; ++i2) dst[i2 * N + j2] = col[i2];
             }
         }
     }
@@ -112,33 +109,35 @@ __global__ void __launch_bounds__(NT) matrix_q_kernel(const int64_t ncells, cons
             const int buf = (i1 * N + i2) & 1;
             double *T2 = sT2 + buf * NR * C * T2SZ;
             // ---- phase A: contract q1 for this (i1, i2)
-            for (int t = threadIdx.x; t < C * NQ * N2; t += NT) {
-                const int c = t / (NQ * N2);
-                const int r = t - c * (NQ * N2);
-                const int q0 = r / N2;
-                const int j12 = r - q0 * N2;
-                const int j1 = j12 / N, j2 = j12 - j1 * N;
-                const double *t1 = sT1 + c * T1SZ + (q0 * NQ) * N2 + i2 * N + j2;
-                if constexpr (FORM == SF_LAPLACE) {
-                    const double *t1d = t1 + C * T1SZ;
-                    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            {
+                cptr<double> bi = fresh(BT + i1 * NQ); // B[q1][i1]
+                cptr<double> di = fresh(DT + i1 * NQ); // D[q1][i1]
+                for (int t = threadIdx.x; t < C * NQ * N2; t += NT) {
+                    const int c = t / (NQ * N2);
+                    const int r = t - c * (NQ * N2);
+                    const int q0 = r / N2;
+                    const int j12 = r - q0 * N2;
+                    const int j1 = j12 / N, j2 = j12 - j1 * N;
+                    const double *t1 = sT1 + c * T1SZ + (q0 * NQ) * N2 + i2 * N + j2;
+                    if constexpr (FORM == SF_LAPLACE) {
+                        const double *t1d = t1 + C * T1SZ;
+                        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-                    for (int q1 = 0; q1 < NQ; ++q1) {
-                        const double bb = sW[q1] * Bt[q1 * N + i1] * sB[q1 * N + j1];
-                        const double dd = sW[q1] * Dt[q1 * N + i1] * sD[q1 * N + j1];
-                        const double tb = t1[q1 * N2], td = t1d[q1 * N2];
-                        a0 = __builtin_fma(bb, tb, a0);
-                        a1 = __builtin_fma(dd, tb, a1);
-                        a2 = __builtin_fma(bb, td, a2);
+                        for (int q1 = 0; q1 < NQ; ++q1) {
+                            const double tb = t1[q1 * N2], td = t1d[q1 * N2];
+                            const double yb = sBw[q1 * N + j1], yd = sDw[q1 * N + j1];
+                            a0 = __builtin_fma(bi[q1], yb * tb, a0);
+                            a1 = __builtin_fma(di[q1], yd * tb, a1);
+                            a2 = __builtin_fma(bi[q1], yb * td, a2);
+                        }
+                        T2[(0 * C + c) * T2SZ + r] = sCoef[c][0] * a0;
+                        T2[(1 * C + c) * T2SZ + r] = sCoef[c][1] * a1 + sCoef[c][2] * a2;
+                    } else {
+                        double a0 = 0.0;
+#pragma unroll
+                        for (int q1 = 0; q1 < NQ; ++q1) a0 = __builtin_fma(bi[q1], sBw[q1 * N + j1] * t1[q1 * N2], a0);
+                        T2[c * T2SZ + r] = sCoef[c][0] * a0;
                     }
-                    T2[(0 * C + c) * T2SZ + r] = sCoef[c][0] * a0;
-                    T2[(1 * C + c) * T2SZ + r] = sCoef[c][1] * a1 + sCoef[c][2] * a2;
-                } else {
-                    double a0 = 0.0;
-#pragma unroll
-                    for (int q1 = 0; q1 < NQ; ++q1)
-                        a0 = __builtin_fma(sW[q1] * Bt[q1 * N + i1] * sB[q1 * N + j1], t1[q1 * N2], a0);
-                    T2[c * T2SZ + r] = sCoef[c][0] * a0;
                 }
             }
             __syncthreads();
@@ -147,33 +146,28 @@ __global__ void __launch_bounds__(NT) matrix_q_kernel(const int64_t ncells, cons
                 const int c = t / N3;
                 const int j = t - c * N3;
                 const int64_t gc = cell0 + c;
-                if (gc >= ncells) continue;
                 const int j0 = j / N2, j12 = j - j0 * N2;
-                double g[NR][NQ];
+                double g0[NQ], g1[NQ], out[N];
 #pragma unroll
                 for (int q0 = 0; q0 < NQ; ++q0) {
                     const double *t2 = T2 + c * T2SZ + q0 * N2 + j12;
                     if constexpr (FORM == SF_LAPLACE) {
-                        g[0][q0] = sW[q0] * sD[q0 * N + j0] * t2[0];
-                        g[1][q0] = sW[q0] * sB[q0 * N + j0] * t2[C * T2SZ];
+                        g0[q0] = sDw[q0 * N + j0] * t2[0];
+                        g1[q0] = sBw[q0 * N + j0] * t2[C * T2SZ];
                     } else {
-                        g[0][q0] = sW[q0] * sB[q0 * N + j0] * t2[0];
+                        g0[q0] = sBw[q0 * N + j0] * t2[0];
                     }
                 }
-                IO *row = A + gc * int64_t(N3) * N3 + int64_t(i1 * N + i2) * N3 + j;
+                if constexpr (FORM == SF_LAPLACE) {
+                    mv<N, NQ>(DT, g0, out); // out[i0] = sum_q0 D[q0][i0] g0[q0]
+                    apply_rows<N, NQ, true>(BT, g1, out);
+                } else {
+                    mv<N, NQ>(BT, g0, out);
+                }
+                if (gc < ncells) { // computed above in uniform control flow, stored only for real cells
+                    IO *row = A + gc * int64_t(N3) * N3 + int64_t(i1 * N + i2) * N3 + j;
 #pragma unroll
-                for (int i0 = 0; i0 < N; ++i0) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int q0 = 0; q0 < NQ; ++q0) {
-                        if constexpr (FORM == SF_LAPLACE) {
-                            acc = __builtin_fma(Dt[q0 * N + i0], g[0][q0], acc);
-                            acc = __builtin_fma(Bt[q0 * N + i0], g[1][q0], acc);
-                        } else {
-                            acc = __builtin_fma(Bt[q0 * N + i0], g[0][q0], acc);
-                        }
-                    }
-                    row[int64_t(i0) * N2 * N3] = IO(acc);
+                    for (int i0 = 0; i0 < N; ++i0) row[int64_t(i0) * N2 * N3] = IO(out[i0]);
                 }
             }
         }

@@ -22,47 +22,86 @@ template <int NQ> struct Lds3 {
     static constexpr int CS = NQ * S1; // one cell's tensor
 };
 
+// Read-only table pointer in the constant address space.  Every use site
+// takes a fresh copy through an empty asm, so the compiler cannot merge table
+// loads of different stages: each stage reloads its 1-D matrix into scalar
+// registers (s_load) right before its FMAs instead of keeping every table
+// live across the kernel and spilling it into vector-register lanes.
+template <typename T> using cptr = const T __attribute__((address_space(4))) *;
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+template <typename T> __device__ __forceinline__ cptr<T> fresh(const T *p)
+{
+    uint64_t v = uniform_u64(reinterpret_cast<uint64_t>(p));
+    asm volatile("" : "+s"(v));
+    return (cptr<T>)v;
+}
+
 __device__ __forceinline__ double to_d(double x) { return x; }
 __device__ __forceinline__ double to_d(float x) { return static_cast<double>(x); }
 template <typename T> __device__ __forceinline__ T conv(double x) { return static_cast<T>(x); }
 
-// out[q] = sum_i M[q*NI + i] in[i]
-template <int NO, int NI, typename T>
-__device__ __forceinline__ void mv(const T *__restrict__ M, const T (&in)[NI], T (&out)[NO])
+// Same, but the copy cannot be taken before `dep` is computed: a data
+// dependence that orders table loads after earlier arithmetic.
+template <typename T, typename D> __device__ __forceinline__ cptr<T> fresh_after(const T *p, const D &dep)
 {
+    uint64_t v = uniform_u64(reinterpret_cast<uint64_t>(p));
+    asm volatile("" : "+s"(v) : "v"(dep));
+    return (cptr<T>)v;
+}
+
+// One-axis contraction of a register pencil with a row-major NO x NI matrix
+// M (device pointer, wave-uniform): out[q] (=|+=) sum_i M[q*NI + i] in[i].
+// Rows are processed in chunks of R; the table pointer of chunk k is taken
+// after the last output of chunk k-2 exists, so at most two chunks of matrix
+// rows are live in scalar registers while their loads overlap the FMAs of
+// the previous chunk.
+template <int NO, int NI, bool ACC, typename T>
+__device__ __forceinline__ void apply_rows(const T *M, const T (&in)[NI], T (&out)[NO])
+{
+    constexpr int R = (NI >= 8) ? 2 : ((NI >= 4) ? 4 : 8);
 #pragma unroll
-    for (int q = 0; q < NO; ++q) {
-        T acc = M[q * NI] * in[0];
+    for (int q0 = 0; q0 < NO; q0 += R) {
+        cptr<T> m = (q0 >= 2 * R) ? fresh_after(M, out[q0 - R - 1]) : fresh(M);
 #pragma unroll
-        for (int i = 1; i < NI; ++i) acc = __builtin_fma(M[q * NI + i], in[i], acc);
-        out[q] = acc;
+        for (int q = q0; q < q0 + R && q < NO; ++q) {
+            T acc;
+            int i0 = 0;
+            if constexpr (ACC) {
+                acc = out[q];
+            } else {
+                acc = m[q * NI] * in[0];
+                i0 = 1;
+            }
+#pragma unroll
+            for (int i = i0; i < NI; ++i) acc = __builtin_fma(m[q * NI + i], in[i], acc);
+            out[q] = acc;
+        }
     }
 }
 
-// out[i] = sum_q M[q*NI + i] in[q]  (transpose of an NO x NI matrix applied to in[NO])
+// out[q] = sum_i M[q][i] in[i] with M row-major NO x NI
 template <int NO, int NI, typename T>
-__device__ __forceinline__ void mtv(const T *__restrict__ M, const T (&in)[NO], T (&out)[NI])
+__device__ __forceinline__ void mv(const T *M, const T (&in)[NI], T (&out)[NO])
 {
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        T acc = M[i] * in[0];
-#pragma unroll
-        for (int q = 1; q < NO; ++q) acc = __builtin_fma(M[q * NI + i], in[q], acc);
-        out[i] = acc;
-    }
+    apply_rows<NO, NI, false>(M, in, out);
 }
-
-// out[i] += sum_q M[q*NI + i] in[q]
+// out[i] = sum_q M[q][i] in[q], given MT = M^T row-major NI x NO
 template <int NO, int NI, typename T>
-__device__ __forceinline__ void mtv_acc(const T *__restrict__ M, const T (&in)[NO], T (&out)[NI])
+__device__ __forceinline__ void mtv(const T *MT, const T (&in)[NO], T (&out)[NI])
 {
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        T acc = out[i];
-#pragma unroll
-        for (int q = 0; q < NO; ++q) acc = __builtin_fma(M[q * NI + i], in[q], acc);
-        out[i] = acc;
-    }
+    apply_rows<NI, NO, false>(MT, in, out);
+}
+template <int NO, int NI, typename T>
+__device__ __forceinline__ void mtv_acc(const T *MT, const T (&in)[NO], T (&out)[NI])
+{
+    apply_rows<NI, NO, true>(MT, in, out);
 }
 
 // pencil access in an LDS tensor with strides S1, S2 (axis 0, 1, 2)

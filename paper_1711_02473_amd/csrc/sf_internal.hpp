@@ -27,6 +27,8 @@ int lagrange_table(int nn, const double *nodes, int np, const double *pts, doubl
 //   B1[nq][n1], D1[nq][n1]
 //   Dh[nq][nq]  collocation derivative of the Lagrange basis on the GL points
 //   w[nq]       GL weights on [0,1]
+//   then the transposes B0T[n0][nq], D0T[n0][nq], B1T[n1][nq], D1T[n1][nq],
+//   DhT[nq][nq], so that every contraction reads its matrix by contiguous rows.
 struct TabLayout {
     int n0, n1, nq;
     __host__ __device__ constexpr TabLayout(int a, int b, int c) : n0(a), n1(b), nq(c) {}
@@ -36,7 +38,12 @@ struct TabLayout {
     __host__ __device__ constexpr int D1() const { return 2 * nq * n0 + nq * n1; }
     __host__ __device__ constexpr int Dh() const { return 2 * nq * (n0 + n1); }
     __host__ __device__ constexpr int W() const { return 2 * nq * (n0 + n1) + nq * nq; }
-    __host__ __device__ constexpr int size() const { return W() + nq; }
+    __host__ __device__ constexpr int B0T() const { return W() + nq; }
+    __host__ __device__ constexpr int D0T() const { return B0T() + nq * n0; }
+    __host__ __device__ constexpr int B1T() const { return D0T() + nq * n0; }
+    __host__ __device__ constexpr int D1T() const { return B1T() + nq * n1; }
+    __host__ __device__ constexpr int DhT() const { return D1T() + nq * n1; }
+    __host__ __device__ constexpr int size() const { return DhT() + nq * nq; }
 };
 
 // Tables split into three bf16 terms (hi, mid, lo) and single fp16 / bf16
