@@ -1,7 +1,5 @@
 #include "sf_internal.hpp"
 namespace sf {
-int launch_action_vec(const LaunchArgs &) { return SF_ERR_UNSUPPORTED; }
-int launch_matrix_vec(const LaunchArgs &) { return SF_ERR_UNSUPPORTED; }
 int launch_action_mixed(const LaunchArgs &) { return SF_ERR_UNSUPPORTED; }
 }
 extern "C" {
