@@ -53,6 +53,7 @@ def main():
     ap.add_argument("--degrees", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--mixed-degrees", default="4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the action is cell-local; see DESIGN.md "
@@ -134,6 +135,11 @@ def main():
                 "kernel": "action_q_kernel Q_%d Laplace FP64" % dom,
                 "bytes_per_launch": action_bytes_per_cell(dom) * ncells}
 
+    mixed = None
+    if args.mixed_degrees:
+        mixed = mixed_leg(sf, ctx, V, bufs, ncells, [int(x) for x in args.mixed_degrees.split(",")], ms, glob,
+                          max(3, args.steps // 2), stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(degrees, bufs, V, glob, ncells, args.cpu_seconds)
@@ -146,10 +152,47 @@ def main():
         "data": "synthetic (seeded box mesh, kappa U[0.5,2], u N(0,1))",
         "config": {"workload": "Q_p Laplace action, p=%s, 64^3 box cells, (p+1)^3 GL points, FP64"
                    % ",".join(map(str, degrees)), "ncells": ncells, "degrees": degrees},
-        "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p,
+        "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p, "mixed_precision": mixed,
     }
     print(json.dumps(out))
     ctx.close()
+
+
+def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
+    """Laplace action with MFMA contractions (BF16 / FP16 single term, BF16 x3
+    split) against the FP64 GPU path on the same inputs (FP64 storage): rate,
+    speed-up and relative L2 difference over the whole output."""
+    import torch
+
+    out = {}
+    for p in degrees:
+        if p not in bufs:
+            continue
+        kap, u, y = bufs[p][0]
+        ref = torch.empty_like(y)
+        sf.assemble_action(ctx, sf.make_op("Q", p, "LAPLACE"), ncells, V, kap, u, ref, stream)
+        row = {}
+        for mode in ("bf16", "fp16", "bf16x3"):
+            op = sf.make_op("Q", p, "LAPLACE", precision=mode)
+            ym = torch.empty_like(y)
+            sf.assemble_action(ctx, op, ncells, V, kap, u, ym, stream)
+            torch.cuda.synchronize()
+            ts = []
+            for it in range(reps):
+                k2, u2, _ = bufs[p][it % len(bufs[p])]
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                sf.assemble_action(ctx, op, ncells, V, k2, u2, ym, stream)
+                b.record(stream)
+                ts.append((a, b))
+            torch.cuda.synchronize()
+            sf.assemble_action(ctx, op, ncells, V, kap, u, ym, stream)
+            err = float(torch.linalg.vector_norm(ym - ref) / torch.linalg.vector_norm(ref))
+            t = float(np.mean([a.elapsed_time(b) for a, b in ts]))
+            row[mode] = {"ms": round(t, 4), "gdofs_global": round(glob[p] / (t / 1e3) / 1e9, 3),
+                         "speedup_vs_fp64": round(ms64[p] / t, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err)}
+        out[str(p)] = row
+    return out
 
 
 def cpu_baseline(degrees, bufs, V, glob, ncells, budget):

@@ -57,6 +57,57 @@ int check_op(const sf_op *op, Dims *d)
     return SF_OK;
 }
 
+// round-to-nearest-even conversions for the low-precision table planes
+uint16_t bf16_bits(double v)
+{
+    float f = float(v);
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return uint16_t(u >> 16);
+}
+double bf16_value(uint16_t b)
+{
+    uint32_t u = uint32_t(b) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return double(f);
+}
+uint16_t fp16_bits(double v)
+{
+    _Float16 h = _Float16(float(v));
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+
+// Mixed-precision table planes (layout shared with mixed.hip): for the
+// matrices B [nq][n], Dh [nq][nq], B^T [n][nq], Dh^T [nq][nq], four 16x16
+// uint16 planes each: bf16 hi, mid, lo (v = hi + mid + lo to about 24 bits)
+// and fp16.
+std::vector<uint16_t> mixed_planes(const std::vector<double> &h, const TabLayout &L, int n, int nq)
+{
+    std::vector<uint16_t> m(4 * 4 * 256, 0);
+    struct Mat { int off, rows, cols; } mats[4] = {{L.B0(), nq, n}, {L.Dh(), nq, nq}, {L.B0T(), n, nq}, {L.DhT(), nq, nq}};
+    for (int k = 0; k < 4; ++k)
+        for (int r = 0; r < mats[k].rows; ++r)
+            for (int c = 0; c < mats[k].cols; ++c) {
+                const double v = h[mats[k].off + size_t(r) * mats[k].cols + c];
+                const uint16_t hi = bf16_bits(v);
+                const double r1 = v - bf16_value(hi);
+                const uint16_t mid = bf16_bits(r1);
+                const uint16_t lo = bf16_bits(r1 - bf16_value(mid));
+                uint16_t *base = m.data() + k * 1024 + r * 16 + c;
+                base[0] = hi;
+                base[256] = mid;
+                base[512] = lo;
+                base[768] = fp16_bits(v);
+            }
+    return m;
+}
+
 int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out)
 {
     auto key = std::make_tuple(int(op->family), int(op->degree), d.nq1);
@@ -102,6 +153,20 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
         (void)hipFree(ts.d64);
         (void)hipFree(ts.f32);
         return SF_ERR_HIP;
+    }
+    if (op->family == SF_Q || op->family == SF_DQ) {
+        std::vector<uint16_t> mp = mixed_planes(h, L, d.n0, d.nq1);
+        if (hipMalloc(&ts.mixed, sizeof(uint16_t) * mp.size()) != hipSuccess) {
+            (void)hipFree(ts.d64);
+            (void)hipFree(ts.f32);
+            return SF_ERR_NOMEM;
+        }
+        if (hipMemcpy(ts.mixed, mp.data(), sizeof(uint16_t) * mp.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(ts.d64);
+            (void)hipFree(ts.f32);
+            (void)hipFree(ts.mixed);
+            return SF_ERR_HIP;
+        }
     }
     auto res = ctx->tables.emplace(key, ts);
     *out = &res.first->second;

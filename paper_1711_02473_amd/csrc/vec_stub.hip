@@ -1,6 +1,5 @@
 #include "sf_internal.hpp"
 namespace sf {
-int launch_action_mixed(const LaunchArgs &) { return SF_ERR_UNSUPPORTED; }
 }
 extern "C" {
 int sf_batch_create(sf_context *, const sf_job *, int32_t, sf_batch **) { return SF_ERR_UNSUPPORTED; }

@@ -1,0 +1,71 @@
+"""Mixed-precision actions (MFMA contractions, FP32 accumulation, FP64 geometry)
+against the FP64 oracle.  BF16X3 (three-term split operands) must reach
+relative L2 <= 1e-6; single-term BF16 / FP16 have no accuracy target in the
+paper and are checked against loose bounds derived from their unit roundoff
+(2^-9 and 2^-12 relative per rounding, a dozen contractions deep)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1711_02473_amd as sf
+from paper_1711_02473_amd import synth
+from tests.gpu_util import dev, empty, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {"bf16x3": 1e-6, "fp16": 2e-2, "bf16": 1.5e-1}
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = sf.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, op, V, kap, u, io=np.float64):
+    n = len(V)
+    nd, _ = sf.sf_element_dims(op)
+    dy = empty((n, nd), io)
+    sf.assemble_action(ctx, op, n, dev(V), dev(kap.astype(io)) if kap is not None else None, dev(u.astype(io)), dy)
+    return host(dy), sf.sf_check_errors(ctx)
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16", "bf16"])
+@pytest.mark.parametrize("family,form", [("Q", "LAPLACE"), ("Q", "MASS"), ("DQ", "LAPLACE")])
+@pytest.mark.parametrize("p", range(1, 9))
+def test_mixed_action_error(ctx, mode, family, form, p):
+    grid = (5, 5, 7) if p <= 3 else (3, 4, 5)
+    V = synth.box_mesh(*grid, 90 + p)
+    n = len(V)
+    nd = (p + 1) ** 3
+    kap = synth.kappa(n, nd, 90 + p)
+    u = synth.dof_vector(n, nd, 90 + p)
+    y, flags = run(ctx, sf.make_op(family, p, form, precision=mode), V, kap, u)
+    ref = oracle.action(family, p, form, V, u, kappa=kap)
+    err = rel_l2(y, ref)
+    print("mixed", mode, family, form, p, "rel_l2 %.3e" % err, flush=True)
+    assert flags == 0
+    assert err <= BOUND[mode], err
+
+
+@pytest.mark.parametrize("p", [2, 8])
+def test_mixed_affine_f32_io(ctx, p):
+    V = synth.affine_cells(33, 95)
+    nd = (p + 1) ** 3
+    u = synth.dof_vector(len(V), nd, 95)
+    y, flags = run(ctx, sf.make_op("Q", p, "LAPLACE", precision="bf16x3", io="f32"), V, None, u, io=np.float32)
+    ref = oracle.action("Q", p, "LAPLACE", V, u.astype(np.float32).astype(np.float64))
+    assert flags == 0
+    assert rel_l2(y, ref) <= 1e-6
+
+
+def test_mixed_unsupported_for_vector_families(ctx):
+    op = sf.make_op("NCF", 2, "HDIV", precision="bf16")
+    V = synth.box_mesh(1, 1, 2, 96)
+    nd, _ = sf.sf_element_dims(op)
+    u = dev(synth.dof_vector(2, nd, 96))
+    y = empty((2, nd), np.float64)
+    with pytest.raises(sf.SfError) as e:
+        sf.assemble_action(ctx, op, 2, dev(V), None, u, y)
+    assert e.value.code == sf.SF_ERR_UNSUPPORTED
