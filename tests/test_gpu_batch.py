@@ -1,0 +1,149 @@
+"""Batched persistent launch captured in a hipGraph: many meshes of mixed
+degree, actions (FP64, BF16, BF16x3) and element matrices in one launch.
+Every graph replay is checked against the stand-alone kernels on the same
+inputs (identical arithmetic per cell) and sampled cells against the oracle."""
+import json
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1711_02473_amd as sf
+from paper_1711_02473_amd import synth
+from tests.gpu_util import dev, empty, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = sf.Context(0)
+    yield c
+    c.close()
+
+
+def make_jobs(seed=5):
+    """A mixed batch: (kind, p, grid) with kind in act_fp64 / act_bf16 / act_bf16x3 / mat."""
+    spec = [("act", "fp64", 2, (5, 4, 6)), ("act", "fp64", 8, (3, 3, 4)), ("mat", "fp64", 3, (2, 2, 3)),
+            ("act", "bf16x3", 5, (4, 4, 3)), ("act", "bf16", 4, (3, 5, 2)), ("mat", "fp64", 7, (1, 1, 3)),
+            ("act", "fp64", 1, (7, 7, 7)), ("act", "bf16x3", 8, (2, 2, 3)), ("mat", "fp64", 8, (1, 1, 2))]
+    jobs = []
+    for i, (kind, prec, p, grid) in enumerate(spec):
+        V = synth.box_mesh(*grid, 100 + i)
+        n = len(V)
+        nd = (p + 1) ** 3
+        kap = synth.kappa(n, nd, 100 + i)
+        rec = {"kind": kind, "prec": prec, "p": p, "V": V, "kap": kap, "n": n, "nd": nd,
+               "dV": dev(V), "dk": dev(kap)}
+        if kind == "act":
+            rec["u"] = synth.dof_vector(n, nd, 100 + i)
+            rec["du"] = dev(rec["u"])
+            rec["dy"] = empty((n, nd), np.float64)
+        else:
+            rec["dA"] = empty((n, nd, nd), np.float64)
+        jobs.append(rec)
+    return jobs
+
+
+def sf_jobs(jobs):
+    out = []
+    for r in jobs:
+        op = sf.make_op("Q", r["p"], "LAPLACE", precision=r["prec"])
+        if r["kind"] == "act":
+            out.append(sf.make_job(op, r["n"], r["dV"], kappa=r["dk"], u=r["du"], y=r["dy"]))
+        else:
+            out.append(sf.make_job(op, r["n"], r["dV"], kappa=r["dk"], A=r["dA"]))
+    return out
+
+
+def standalone(ctx, r):
+    op = sf.make_op("Q", r["p"], "LAPLACE", precision=r["prec"])
+    if r["kind"] == "act":
+        y = empty((r["n"], r["nd"]), np.float64)
+        sf.assemble_action(ctx, op, r["n"], r["dV"], r["dk"], r["du"], y)
+        return host(y)
+    A = empty((r["n"], r["nd"], r["nd"]), np.float64)
+    sf.assemble_element_matrix(ctx, op, r["n"], r["dV"], r["dk"], A)
+    return host(A)
+
+
+def test_batch_graph_replays_match_standalone_and_oracle(ctx):
+    import torch
+    jobs = make_jobs()
+    refs = [standalone(ctx, r) for r in jobs]
+    batch = sf.Batch(ctx, sf_jobs(jobs))
+    ntiles, nwg = batch.info()
+    assert ntiles >= len(jobs) and nwg >= 1
+    for rep in range(3):
+        # eager work between replays: clear every output with torch, synchronise
+        for r in jobs:
+            (r["dy"] if r["kind"] == "act" else r["dA"]).fill_(float("nan"))
+        torch.cuda.synchronize()
+        batch.launch()
+        torch.cuda.synchronize()
+        assert sf.sf_check_errors(ctx) == 0
+        for r, ref in zip(jobs, refs):
+            got = host(r["dy"] if r["kind"] == "act" else r["dA"])
+            assert np.isfinite(got).all(), (rep, r["kind"], r["p"])
+            assert rel_l2(got, ref) <= 1e-14, (rep, r["kind"], r["prec"], r["p"], rel_l2(got, ref))
+    # oracle on a sample of cells of every job
+    for r, ref in zip(jobs, refs):
+        idx = np.unique(np.linspace(0, r["n"] - 1, 4).astype(int))
+        tol = {"fp64": 1e-12, "bf16x3": 1e-6, "bf16": 1.5e-1}[r["prec"]]
+        if r["kind"] == "act":
+            o = oracle.action("Q", r["p"], "LAPLACE", r["V"][idx], r["u"][idx], kappa=r["kap"][idx])
+            assert rel_l2(ref[idx], o) <= tol
+        else:
+            o = oracle.element_matrix("Q", r["p"], "LAPLACE", r["V"][idx], kappa=r["kap"][idx])
+            assert rel_l2(ref[idx], o) <= tol
+    batch.close()
+
+
+def test_batch_arena_cycles_element_matrices(ctx):
+    """Element matrices go to slot c % arena; with identical cells every slot holds the one matrix."""
+    p = 4
+    n = 23
+    V = np.repeat(synth.box_mesh(1, 1, 1, 7), n, axis=0)
+    nd = (p + 1) ** 3
+    A = empty((5, nd, nd), np.float64)
+    A.fill_(float("nan"))
+    op = sf.make_op("Q", p, "LAPLACE")
+    batch = sf.Batch(ctx, [sf.make_job(op, n, dev(V), A=A, A_arena_cells=5)])
+    batch.launch()
+    got = host(A)
+    ref = oracle.element_matrix("Q", p, "LAPLACE", V[:1])[0]
+    for s in range(5):
+        assert rel_l2(got[s], ref) <= 1e-12
+    batch.close()
+
+
+def test_batch_rejects_bad_jobs(ctx):
+    V = dev(synth.box_mesh(1, 1, 2, 8))
+    u = dev(synth.dof_vector(2, 27, 8))
+    y = empty((2, 27), np.float64)
+    with pytest.raises(sf.SfError) as e:  # vector family not in the fused kernel
+        sf.Batch(ctx, [sf.make_job(sf.make_op("NCF", 2, "HDIV"), 2, V, u=u, y=y)])
+    assert e.value.code == sf.SF_ERR_UNSUPPORTED
+    with pytest.raises(sf.SfError) as e:  # action without output
+        sf.Batch(ctx, [sf.make_job(sf.make_op("Q", 2, "LAPLACE"), 2, V, u=u)])
+    assert e.value.code == sf.SF_ERR_ARG
+    b = sf.Batch(ctx, [])  # empty batch is valid and does nothing
+    b.launch()
+    b.close()
+
+
+def test_autotune_cache_roundtrip(ctx):
+    op = sf.make_op("Q", 3, "LAPLACE")
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        sf.sf_autotune(ctx, op, 20000, path)
+        v = sf.sf_tuned_variant(ctx, op)
+        assert 0 <= v < 5
+        data = json.load(open(path))
+        assert any(k.startswith("gfx950|fam0|p3|form1") for k in data)
+        c2 = sf.Context(0)
+        sf.sf_load_tuning(c2, path)
+        assert sf.sf_tuned_variant(c2, op) == v
+        c2.close()
