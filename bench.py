@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--mixed-degrees", default="4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with one 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the action is cell-local; see DESIGN.md "
@@ -154,6 +156,13 @@ def main():
                    % ",".join(map(str, degrees)), "ncells": ncells, "degrees": degrees},
         "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p, "mixed_precision": mixed,
     }
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 1 << 30
     print(json.dumps(out))
     ctx.close()
 
