@@ -9,7 +9,8 @@ local-DOF rates, roofline fractions and the mixed-precision comparison are
 reported beside it.  Inputs are resident in HBM before timing; several input
 copies are rotated so that every launch streams more than the 256 MB
 last-level cache.  Kernel durations come from HIP events recorded on the
-stream the kernels run on.
+stream the kernels run on.  The library is told that every cell is a box
+(sf_set_geometry) and each degree's kernel variant is autotuned first.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -18,6 +19,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -54,6 +56,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--mixed-degrees", default="4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
+    ap.add_argument("--no-tune", action="store_true", help="skip sf_autotune (library defaults)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -80,16 +83,18 @@ def main():
         n3 = (p + 1) ** 3
         per_set = 3 * 8 * n3 * ncells
         nsets = max(1, min(6, math.ceil(768e6 / per_set)))
-        g = torch.Generator(device="cuda")
-        g.manual_seed(171102473 * 100 + 2 * 10 + p)
-        sets = []
-        for _ in range(nsets):
-            kap = torch.rand((ncells, n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
-            u = torch.randn((ncells, n3), generator=g, device="cuda", dtype=torch.float64)
-            y = torch.empty_like(u)
-            sets.append((kap, u, y))
-        bufs[p] = sets
+        bufs[p] = [(kap, u, torch.empty_like(u)) for kap, u in synth.device_action_inputs(ncells, n3, 2, p, nsets)]
     ops = {p: sf.make_op("Q", p, "LAPLACE") for p in degrees}
+    # every cell is an axis-aligned box: the library may use its box-cell kernels
+    sf.sf_set_geometry(ctx, "box")
+    tuned = {}
+    if not args.no_tune:
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "tune.json")
+            for p in degrees:
+                sf.sf_autotune(ctx, ops[p], ncells, path)
+            with open(path) as f:
+                tuned = json.load(f)
     torch.cuda.synchronize()
 
     def step(timers=None, it=0):
@@ -134,7 +139,7 @@ def main():
     achieved = action_bytes_per_cell(dom) * ncells / (ms[dom] / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": "action_q_kernel Q_%d Laplace FP64" % dom,
+                "kernel": "action_q_fast_kernel Q_%d Laplace FP64" % dom,
                 "bytes_per_launch": action_bytes_per_cell(dom) * ncells}
 
     mixed = None
@@ -155,6 +160,7 @@ def main():
         "config": {"workload": "Q_p Laplace action, p=%s, 64^3 box cells, (p+1)^3 GL points, FP64"
                    % ",".join(map(str, degrees)), "ncells": ncells, "degrees": degrees},
         "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p, "mixed_precision": mixed,
+        "tuned_variants": {k.split("|", 1)[1]: v for k, v in tuned.items()},
     }
     if args.calib_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)

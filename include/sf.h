@@ -105,6 +105,20 @@ int sf_context_destroy(sf_context *ctx);
 /* Human-readable text of a status code (static storage). */
 const char *sf_status_string(int status);
 
+/* Geometry class the caller guarantees for later calls on this context.
+ * SF_GEOM_AFFINE (the default): any affine cell (parallelepipeds, boxes).
+ * SF_GEOM_BOX: every cell is an axis-aligned box (J diagonal); the Q_p /
+ * dQ_p actions then use kernels that exploit the diagonal factor |J| G G^T
+ * (two LDS tensors per cell instead of three).  Under SF_GEOM_BOX a cell
+ * whose Jacobian has off-diagonal entries raises SF_FLAG_NONBOX in the
+ * Laplace action and its output is unspecified (the mass action needs only
+ * |det J| and stays exact on any affine cell).  The hint does not change
+ * element matrices or the H(div) / H(curl) kernels.  Returns SF_ERR_ARG for
+ * an unknown value. */
+#define SF_GEOM_AFFINE 0
+#define SF_GEOM_BOX 1
+int sf_set_geometry(sf_context *ctx, int32_t geometry);
+
 /* Host only, no GPU needed.  Per-cell local DOF count and quadrature-point
  * count of `op` (after nq1 = 0 => degree + 1), or an error for an
  * unsupported combination.  Validation rules are exactly those of the
@@ -222,12 +236,17 @@ int sf_batch_destroy(sf_batch *batch);
 int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
 
 /*
- * Tile autotuner: times the compiled tile variants of `op` (cells per
- * workgroup) on ncells_hint synthetic cells on an internal stream and records
- * the fastest in the context (and, when cache_json_path is non-NULL, merges
- * it into that JSON file, keyed by architecture, family, degree, form, nq1,
- * precision and io dtype).  Later calls with the same key use the winner.
- * sf_tuned_variant() returns the variant currently selected (0 = default).
+ * Tile autotuner for the Q_p Laplace action: times, on ncells_hint synthetic
+ * unit-box cells on an internal stream, (1) the tile size of the batched
+ * launch (1, 2, 4, 8 or 16 cell groups per tile; variants 0..4) and (2) for
+ * FP64 / FP32 the stand-alone box-cell kernel variants (0: prefetch of the
+ * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 4; 2:
+ * prefetch, >= 2; 3: the general three-tensor kernel that SF_GEOM_AFFINE
+ * uses), and records the fastest of each in the context (and, when
+ * cache_json_path is non-NULL, merges them into that JSON file, keyed by
+ * architecture, family, degree, form, nq1, precision, io dtype and
+ * "batch" / "standalone").  Later calls with the same key use the winners.
+ * sf_tuned_variant() returns the batched tile variant (default 2).
  */
 int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const char *cache_json_path);
 int sf_tuned_variant(sf_context *ctx, const sf_op *op, int32_t *variant);

@@ -24,6 +24,7 @@ SF_ERR_HIP = -4
 SF_ERR_GEOMETRY = -5
 SF_ERR_CAPACITY = -6
 SF_FLAG_DETJ, SF_FLAG_NONAFFINE, SF_FLAG_NONBOX = 1, 2, 4
+SF_GEOM_AFFINE, SF_GEOM_BOX = 0, 1
 
 
 class SfOp(ctypes.Structure):
@@ -63,6 +64,7 @@ def load(path=LIB_PATH):
         "sf_context_destroy": ([vp], ctypes.c_int),
         "sf_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "sf_element_dims": ([opp, ip, ip], ctypes.c_int),
+        "sf_set_geometry": ([vp, i32], ctypes.c_int),
         "assemble_action": ([vp, opp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "assemble_element_matrix": ([vp, opp, i64, vp, vp, vp, vp], ctypes.c_int),
         "sf_check_errors": ([vp, vp, ip], ctypes.c_int),
@@ -138,6 +140,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def sf_set_geometry(ctx, geometry):
+    """SF_GEOM_AFFINE (default) or SF_GEOM_BOX (the caller guarantees axis-aligned boxes)."""
+    g = {"affine": SF_GEOM_AFFINE, "box": SF_GEOM_BOX}.get(geometry, geometry)
+    return _check(_lib().sf_set_geometry(ctx.handle, int(g)), "sf_set_geometry")
 
 
 def sf_element_dims(op):

@@ -1,0 +1,375 @@
+// Operator action for Q_p / dQ_p (mass, Laplace), FP64 or FP32 contractions:
+// the production kernel behind assemble_action.
+//
+// Same mathematics as action_q_body.inc (interpolate to the Gauss points with
+// B, collocated derivative Dh, pointwise factor, transposed contractions;
+// Sec. 3.3 eq. coeff_eval / eq. form_eval), organised for occupancy and
+// latency on gfx950:
+//
+// * Axis-aligned box cells only (selected by sf_set_geometry(SF_GEOM_BOX)):
+//   |J| G G^T is diagonal, so the Laplacian splits into three independent
+//   directional chains Dh_a^T (w kappa P_aa) Dh_a.  Each chain runs inside
+//   one pencil orientation - gradient, pointwise factor and transposed
+//   gradient in registers - and accumulates into one LDS tensor: two LDS
+//   tensors per cell instead of three.  A cell with off-diagonal J raises
+//   SF_FLAG_NONBOX (only the diagonal factor is applied to it).
+// * Persistent workgroups: each one walks cell groups g, g + G, ... and
+//   issues the next group's u, kappa and vertex loads into registers right
+//   after the current values are consumed, so HBM latency overlaps compute.
+//   u / kappa / y are touched through x-axis pencils (consecutive lanes,
+//   consecutive addresses).
+#include <algorithm>
+
+#include "sf_device.hpp"
+#include "sf_internal.hpp"
+
+namespace sf {
+
+template <int N, int NQ, int FORM, bool COLL, typename T, int C> struct ActionFastSmem {
+    static constexpr int NB = (FORM == SF_LAPLACE) ? 2 : 1;
+    static constexpr int tensor_bytes = NB * C * Lds3<NQ>::CS * int(sizeof(T));
+    static constexpr int bytes = tensor_bytes + 8 * (6 * C + 24 * C) + 16 * C;
+};
+
+// PREF: prefetch the next group's inputs into registers (more registers,
+// latency overlap) or load them when needed; MINB: workgroups per CU the
+// register allocation must allow.
+template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, int NT, bool PREF, int MINB>
+__global__ void __launch_bounds__(NT, MINB)
+    action_q_fast_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
+                         const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab,
+                         int *__restrict__ err)
+{
+    static_assert(N == NQ, "the fast kernel assumes n Gauss points per axis");
+    using L = Lds3<NQ>;
+    constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
+    constexpr int NB = (FORM == SF_LAPLACE) ? 2 : 1;
+    constexpr TabLayout TL(N, 0, NQ);
+    constexpr int N2 = N * N, N3 = N2 * N;
+    const T *const Bt = tab + TL.B0();
+    const T *const BtT = tab + TL.B0T();
+    const T *const Dh = tab + TL.Dh();
+    const T *const DhT = tab + TL.DhT();
+    const T *const tW = tab + TL.W();
+
+    __shared__ T lds[NB * C * CS];
+    __shared__ double sP[C][6];
+    __shared__ double sV[C][24];
+    T *const L0 = lds;
+    T *const L1 = lds + (NB - 1) * C * CS;
+
+    const int64_t ngroups = (ncells + C - 1) / C;
+    const bool has_kappa = kappa != nullptr;
+    const int tid = threadIdx.x;
+    // this thread's x-pencil in the HBM stages (stage 1: u; the x stage: kappa)
+    const bool pen = tid < C * N2;
+    const int pc = pen ? tid / N2 : 0, pr = tid - pc * N2, pa = pr / N, pb = pr - pa * N;
+    // the group's 24 C vertex coordinates, VR per thread (contiguous in HBM)
+    constexpr int VR = (24 * C + NT - 1) / NT;
+
+    T ureg[N], kreg[NQ];
+    double vreg[VR];
+    auto load_v = [&](int64_t g) {
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            const int t = tid + r * NT;
+            vreg[r] = (t < 24 * C && g * C + t / 24 < ncells) ? vert[g * C * 24 + t] : 0.0;
+        }
+    };
+    auto load_u = [&](int64_t g) {
+        const int64_t gc = g * C + pc;
+        const bool ok = pen && gc < ncells;
+#pragma unroll
+        for (int i = 0; i < N; ++i) ureg[i] = ok ? T(to_d(u[gc * N3 + i * N2 + pr])) : T(0);
+    };
+    auto load_k = [&](int64_t g) {
+        const int64_t gc = g * C + pc;
+        const bool ok = pen && has_kappa && gc < ncells;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) kreg[i] = ok ? T(to_d(kappa[gc * N3 + i * N2 + pr])) : T(1);
+    };
+
+    int64_t g = blockIdx.x;
+    if (PREF && g < ngroups) {
+        load_v(g);
+        load_u(g);
+        if constexpr (FORM == SF_LAPLACE) load_k(g);
+    }
+    for (; g < ngroups; g += gridDim.x) {
+        const int64_t gn = g + gridDim.x;
+        const bool more = PREF && gn < ngroups;
+        const int64_t cell0 = g * C;
+        if (!PREF) {
+            load_v(g);
+            load_u(g);
+        }
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            const int t = tid + r * NT;
+            if (t < 24 * C) sV[t / 24][t % 24] = vreg[r];
+        }
+        if (more) load_v(gn);
+        __syncthreads(); // vertices staged; the previous group's last LDS reads are done
+
+        // ---- geometry (FP64): J, det, |J| G G^T (or |J|), box test
+        if (tid < C) {
+            double P[6] = {0, 0, 0, 0, 0, 0};
+            if (cell0 + tid < ncells) {
+                double J[3][3], det;
+                int f = affine_jacobian(sV[tid], J, det);
+                if (FORM == SF_LAPLACE) {
+                    laplace_factor(J, det, P);
+                    const double off = fabs(J[0][1]) + fabs(J[0][2]) + fabs(J[1][0]) + fabs(J[1][2]) +
+                                       fabs(J[2][0]) + fabs(J[2][1]);
+                    const double dia = fabs(J[0][0]) + fabs(J[1][1]) + fabs(J[2][2]);
+                    if (off > 1e-14 * dia) f |= SF_FLAG_NONBOX; // only the diagonal of G G^T is applied
+                } else {
+                    P[0] = fabs(det);
+                }
+                if (f) atomicOr(err, f);
+            }
+#pragma unroll
+            for (int t = 0; t < 6; ++t) sP[tid][t] = P[t];
+        }
+
+        if constexpr (COLL && FORM == SF_MASS) {
+            // collocated mass: diagonal operator, y = w kappa |J| u, no LDS tensors
+            __syncthreads();
+            if (pen && cell0 + pc < ncells) {
+                cptr<T> W = fresh(tW);
+                const T s23 = T(sP[pc][0]) * W[pa] * W[pb];
+                const int64_t base = (cell0 + pc) * N3 + pr;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    T om = s23 * W[i];
+                    if (has_kappa) om *= T(to_d(kappa[base + i * N2]));
+                    y[base + i * N2] = IO(om * ureg[i]);
+                }
+            }
+            if (more) load_u(gn);
+            continue;
+        } else {
+            // ---- stage 1 (x): u -> B_x u
+            if (pen) {
+                if constexpr (COLL) {
+                    st_pencil<0, N, S1, S2>(L0 + pc * CS, pa, pb, ureg);
+                } else {
+                    T out[NQ];
+                    mv<NQ, N>(Bt, ureg, out);
+                    st_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, out);
+                }
+            }
+            if (more) load_u(gn);
+            __syncthreads();
+            // ---- stage 2 (y): B_y
+            if constexpr (!COLL) {
+                pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
+                    T in[N], out[NQ];
+                    ld_pencil<1, N, S1, S2>(L0 + c * CS, q1, i3, in);
+                    mv<NQ, N>(Bt, in, out);
+                    st_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, i3, out);
+                });
+                __syncthreads();
+            }
+
+            if constexpr (FORM == SF_MASS) {
+                // ---- stage 3 (z): B_z, w kappa |J|, B_z^T
+                pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
+                    const int64_t gc = cell0 + c;
+                    T in[N], ut[NQ], t[N];
+                    ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
+                    mv<NQ, N>(Bt, in, ut);
+                    cptr<T> W = fresh(tW);
+                    const T w12 = T(sP[c][0]) * W[q1] * W[q2];
+#pragma unroll
+                    for (int q3 = 0; q3 < NQ; ++q3) {
+                        T om = w12 * W[q3];
+                        if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * N3 + (q1 * NQ + q2) * NQ + q3]));
+                        ut[q3] *= om;
+                    }
+                    mtv<NQ, N>(BtT, ut, t);
+                    st_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, t);
+                });
+                __syncthreads();
+            } else {
+                // ---- box path.  stage 3 (z): u~ = B_z(.), store u~; w = Dh_z^T (w kappa P_zz Dh_z u~)
+                pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
+                    const int64_t gc = cell0 + c;
+                    T ut[NQ], gz[NQ];
+                    if constexpr (COLL) {
+                        ld_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, ut);
+                    } else {
+                        T in[N];
+                        ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
+                        mv<NQ, N>(Bt, in, ut);
+                        st_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, ut);
+                    }
+                    mv<NQ, NQ>(Dh, ut, gz);
+                    cptr<T> W = fresh(tW);
+                    const T w12 = T(sP[c][5]) * W[q1] * W[q2];
+#pragma unroll
+                    for (int q3 = 0; q3 < NQ; ++q3) {
+                        T om = w12 * W[q3];
+                        if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * N3 + (q1 * NQ + q2) * NQ + q3]));
+                        gz[q3] *= om;
+                    }
+                    mtv<NQ, NQ>(DhT, gz, ut);
+                    st_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, ut);
+                });
+                __syncthreads();
+                // ---- stage 4 (y): w += Dh_y^T (w kappa P_yy Dh_y u~)
+                pencils<C, NQ, NQ, NT>([&](int c, int q1, int q3) {
+                    const int64_t gc = cell0 + c;
+                    T ut[NQ], gy[NQ], wv[NQ];
+                    ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, ut);
+                    mv<NQ, NQ>(Dh, ut, gy);
+                    cptr<T> W = fresh(tW);
+                    const T w13 = T(sP[c][3]) * W[q1] * W[q3];
+#pragma unroll
+                    for (int q2 = 0; q2 < NQ; ++q2) {
+                        T om = w13 * W[q2];
+                        if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * N3 + (q1 * NQ + q2) * NQ + q3]));
+                        gy[q2] *= om;
+                    }
+                    ld_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
+                    mtv_acc<NQ, NQ>(DhT, gy, wv);
+                    st_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
+                });
+                __syncthreads();
+                // ---- stage 5 (x): w += Dh_x^T (w kappa P_xx Dh_x u~); kappa from the prefetch registers
+                if (!PREF) load_k(g);
+                if (pen) {
+                    T ut[NQ], gx[NQ], wv[NQ];
+                    ld_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, ut);
+                    mv<NQ, NQ>(Dh, ut, gx);
+                    cptr<T> W = fresh(tW);
+                    const T w23 = T(sP[pc][0]) * W[pa] * W[pb];
+#pragma unroll
+                    for (int q1 = 0; q1 < NQ; ++q1) gx[q1] *= w23 * W[q1] * kreg[q1];
+                    ld_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
+                    mtv_acc<NQ, NQ>(DhT, gx, wv);
+                    st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
+                }
+                if (more) load_k(gn);
+                __syncthreads();
+                // ---- backward interpolation, z then y then x; the complete w is in L1
+                if constexpr (!COLL) {
+                    pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
+                        T in[NQ], t[N];
+                        ld_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, in);
+                        mtv<NQ, N>(BtT, in, t);
+                        st_pencil<2, N, S1, S2>(L1 + c * CS, q1, q2, t);
+                    });
+                    __syncthreads();
+                }
+            }
+            T *const LB = (FORM == SF_LAPLACE) ? L1 : L0; // tensor holding the backward data
+            if constexpr (!COLL) {
+                pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
+                    T in[NQ], out[N];
+                    ld_pencil<1, NQ, S1, S2>(LB + c * CS, q1, i3, in);
+                    mtv<NQ, N>(BtT, in, out);
+                    st_pencil<1, N, S1, S2>(LB + c * CS, q1, i3, out);
+                });
+                __syncthreads();
+            }
+            // ---- last stage (x): B_x^T, store y (coalesced)
+            if (pen && cell0 + pc < ncells) {
+                T in[NQ], out[N];
+                ld_pencil<0, NQ, S1, S2>(LB + pc * CS, pa, pb, in);
+                if constexpr (COLL) {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) out[i] = in[i];
+                } else {
+                    mtv<NQ, N>(BtT, in, out);
+                }
+                IO *yo = y + (cell0 + pc) * N3 + pr;
+#pragma unroll
+                for (int i = 0; i < N; ++i) yo[i * N2] = IO(out[i]);
+            }
+        }
+    }
+}
+
+namespace {
+
+template <typename K> int grid_for(K kernel, int nt, int64_t groups, int *cache)
+{
+    if (*cache <= 0) {
+        int per_cu = 0, ncu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return -1;
+        *cache = std::max(1, per_cu) * std::max(1, ncu);
+    }
+    return int(std::min<int64_t>(groups, *cache));
+}
+
+template <int N, int FORM, bool COLL, typename T, typename IO, bool PREF, int MINB>
+int launch_fast_v(const LaunchArgs &a, const T *tab)
+{
+    constexpr int NT = 256;
+    constexpr int C = (NT / (N * N)) > 0 ? NT / (N * N) : 1;
+    static int cache = 0;
+    const int64_t groups = (a.ncells + C - 1) / C;
+    auto kern = action_q_fast_kernel<N, N, FORM, COLL, T, IO, C, NT, PREF, MINB>;
+    const int grid = grid_for(kern, NT, groups, &cache);
+    if (grid < 0) return SF_ERR_HIP;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, a.stream, a.ncells, a.vert, static_cast<const IO *>(a.kappa),
+                       static_cast<const IO *>(a.u), static_cast<IO *>(a.y), tab, a.err);
+    return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+// tile variants (autotuner search space): 0 = prefetch, >= 3 workgroups/CU;
+// 1 = no prefetch, >= 4 workgroups/CU; 2 = prefetch, >= 2 workgroups/CU
+template <int N, int FORM, bool COLL, typename T, typename IO>
+int launch_fast(const LaunchArgs &a, const T *tab)
+{
+    switch (a.variant) {
+    case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 4>(a, tab);
+    case 2: return launch_fast_v<N, FORM, COLL, T, IO, true, 2>(a, tab);
+    default: return launch_fast_v<N, FORM, COLL, T, IO, true, 3>(a, tab);
+    }
+}
+
+template <int N, int FORM, bool COLL>
+int fast_prec(const LaunchArgs &a)
+{
+    if (a.precision == SF_FP64)
+        return a.io == SF_F64 ? launch_fast<N, FORM, COLL, double, double>(a, a.tab64)
+                              : launch_fast<N, FORM, COLL, double, float>(a, a.tab64);
+    if (a.precision == SF_FP32)
+        return a.io == SF_F64 ? launch_fast<N, FORM, COLL, float, double>(a, a.tab32)
+                              : launch_fast<N, FORM, COLL, float, float>(a, a.tab32);
+    return SF_ERR_UNSUPPORTED;
+}
+
+template <int N>
+int fast_n(const LaunchArgs &a)
+{
+    const bool coll = a.family == SF_DQ;
+    if (a.form == SF_MASS) return coll ? fast_prec<N, SF_MASS, true>(a) : fast_prec<N, SF_MASS, false>(a);
+    if (a.form == SF_LAPLACE) return coll ? fast_prec<N, SF_LAPLACE, true>(a) : fast_prec<N, SF_LAPLACE, false>(a);
+    return SF_ERR_UNSUPPORTED;
+}
+
+} // namespace
+
+int launch_action_q_fast(const LaunchArgs &a)
+{
+    if (a.nq != a.degree + 1) return SF_ERR_UNSUPPORTED;
+    switch (a.degree + 1) {
+    case 2: return fast_n<2>(a);
+    case 3: return fast_n<3>(a);
+    case 4: return fast_n<4>(a);
+    case 5: return fast_n<5>(a);
+    case 6: return fast_n<6>(a);
+    case 7: return fast_n<7>(a);
+    case 8: return fast_n<8>(a);
+    case 9: return fast_n<9>(a);
+    default: return SF_ERR_UNSUPPORTED;
+    }
+}
+
+} // namespace sf

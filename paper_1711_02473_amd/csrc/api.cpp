@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <string>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -207,6 +209,18 @@ int make_args(sf_context *ctx, const sf_op *op, int64_t ncells, const double *ve
 } // namespace
 
 namespace sf {
+std::string tune_key(const sf_op *op, const char *what)
+{
+    char b[160];
+    snprintf(b, sizeof b, "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|%s", op->family, op->degree, op->form,
+             op->nq1 ? op->nq1 : op->degree + 1, op->precision, op->io_dtype, what);
+    return b;
+}
+int tuned_variant_of(sf_context *ctx, const sf_op *op, const char *what, int dflt)
+{
+    auto it = ctx->tuned.find(tune_key(op, what));
+    return it == ctx->tuned.end() ? dflt : it->second;
+}
 int op_dims(const sf_op *op, int *ndof, int *nq)
 {
     Dims d;
@@ -275,6 +289,13 @@ int sf_context_destroy(sf_context *ctx)
     return SF_OK;
 }
 
+int sf_set_geometry(sf_context *ctx, int32_t geometry)
+{
+    if (!ctx || (geometry != SF_GEOM_AFFINE && geometry != SF_GEOM_BOX)) return SF_ERR_ARG;
+    ctx->geometry = geometry;
+    return SF_OK;
+}
+
 int sf_element_dims(const sf_op *op, int32_t *ndof_cell, int32_t *nq_cell)
 {
     Dims d;
@@ -302,7 +323,14 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     a.y = y;
     if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
         return launch_action_mixed(a);
-    if (op->family == SF_Q || op->family == SF_DQ) return launch_action_q(a);
+    if (op->family == SF_Q || op->family == SF_DQ) {
+        if (ctx->geometry == SF_GEOM_BOX) {
+            // variants 0..2: box-cell kernels; 3: the general three-tensor kernel
+            a.variant = tuned_variant_of(ctx, op, "standalone", 0);
+            return a.variant == 3 ? launch_action_q(a) : launch_action_q_fast(a);
+        }
+        return launch_action_q(a);
+    }
     return launch_action_vec(a);
 }
 

@@ -212,18 +212,9 @@ int kind_of(const sf_job &j)
     }
 }
 
-std::string tune_key(const sf_op *op)
-{
-    char b[128];
-    snprintf(b, sizeof b, "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d", op->family, op->degree, op->form,
-             op->nq1 ? op->nq1 : op->degree + 1, op->precision, op->io_dtype);
-    return b;
-}
-
 int groups_for(sf_context *ctx, const sf_op *op)
 {
-    auto it = ctx->tuned.find(tune_key(op));
-    const int v = it == ctx->tuned.end() ? 2 : it->second;
+    const int v = tuned_variant_of(ctx, op, "batch", 2);
     return kGroupVariants[std::min(std::max(v, 0), 4)];
 }
 
@@ -407,11 +398,12 @@ bool write_json(const char *path, const std::map<std::string, int> &m)
     return bool(f);
 }
 
-__global__ void tune_fill_kernel(int64_t ncells, int n3, double *vert, double *u)
+__global__ void tune_fill_kernel(int64_t ncells, int n3, int nq3, double *vert, double *u, double *kap)
 {
-    const int64_t total = ncells * (n3 > 24 ? n3 : 24);
+    const int64_t total = ncells * std::max(std::max(n3, nq3), 24);
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
         if (t < ncells * n3) u[t] = double((t * 2654435761LL) % 1000) * 1e-3 - 0.5;
+        if (t < ncells * nq3) kap[t] = 1.0 + double((t * 40503LL) % 1000) * 1e-3;
         if (t < ncells * 24) {
             const int v = int((t % 24) / 3), a = int(t % 3);
             vert[t] = double((v >> (2 - a)) & 1);
@@ -456,8 +448,7 @@ int sf_tuned_variant(sf_context *ctx, const sf_op *op, int32_t *variant)
     int nd, nq;
     int rc = op_dims(op, &nd, &nq);
     if (rc) return rc;
-    auto it = ctx->tuned.find(tune_key(op));
-    *variant = it == ctx->tuned.end() ? 2 : it->second;
+    *variant = tuned_variant_of(ctx, op, "batch", 2);
     return SF_OK;
 }
 
@@ -477,14 +468,16 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
     if (rc) return rc;
     if (op->family != SF_Q || op->form != SF_LAPLACE || op->io_dtype != SF_F64) return SF_ERR_UNSUPPORTED;
     const int64_t nc = std::min<int64_t>(ncells_hint, 1 << 20);
-    double *vert = nullptr, *u = nullptr, *y = nullptr;
-    if (hipMalloc(&vert, sizeof(double) * 24 * nc) != hipSuccess) return SF_ERR_NOMEM;
-    if (hipMalloc(&u, sizeof(double) * nd * nc) != hipSuccess || hipMalloc(&y, sizeof(double) * nd * nc) != hipSuccess) {
+    // synthetic unit boxes, u and a kappa per quadrature point, as in a production call
+    double *vert = nullptr, *u = nullptr, *y = nullptr, *kap = nullptr;
+    if (hipMalloc(&vert, sizeof(double) * 24 * nc) != hipSuccess || hipMalloc(&u, sizeof(double) * nd * nc) != hipSuccess ||
+        hipMalloc(&y, sizeof(double) * nd * nc) != hipSuccess || hipMalloc(&kap, sizeof(double) * nq * nc) != hipSuccess) {
         (void)hipFree(vert);
         (void)hipFree(u);
+        (void)hipFree(y);
         return SF_ERR_NOMEM;
     }
-    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, 0, nc, nd, vert, u);
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, 0, nc, nd, nq, vert, u, kap);
     hipStream_t s;
     hipEvent_t e0, e1;
     bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
@@ -498,6 +491,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
         j.op = *op;
         j.ncells = nc;
         j.vertices = vert;
+        j.kappa = kap;
         j.u = u;
         j.y = y;
         int g = kGroupVariants[v];
@@ -522,17 +516,51 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
             best = v;
         }
     }
+    // stand-alone box-cell action kernel variants (prefetch / occupancy)
+    int best_sa = 0;
+    if (ok && (op->precision == SF_FP64 || op->precision == SF_FP32)) {
+        LaunchArgs a;
+        ok = ensure_tables(ctx, op, a) == SF_OK;
+        float best_sa_ms = 1e30f;
+        for (int v = 0; ok && v < 4; ++v) {
+            a.ncells = nc;
+            a.vert = vert;
+            a.kappa = kap;
+            a.u = u;
+            a.y = y;
+            a.stream = s;
+            a.variant = v;
+            auto run = [&] { return v == 3 ? launch_action_q(a) : launch_action_q_fast(a); };
+            ok = run() == SF_OK; // warm-up
+            float tot = 0.0f;
+            for (int r = 0; ok && r < 3; ++r) {
+                ok = hipEventRecord(e0, s) == hipSuccess && run() == SF_OK &&
+                     hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                float ms = 0.0f;
+                ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                tot += ms;
+            }
+            if (ok && tot < best_sa_ms) {
+                best_sa_ms = tot;
+                best_sa = v;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);
     (void)hipFree(vert);
     (void)hipFree(u);
     (void)hipFree(y);
+    (void)hipFree(kap);
     if (!ok) return SF_ERR_HIP;
-    ctx->tuned[tune_key(op)] = best;
+    ctx->tuned[tune_key(op, "batch")] = best;
+    ctx->tuned[tune_key(op, "standalone")] = best_sa;
     if (cache_json_path) {
         auto m = read_json(cache_json_path);
-        m[tune_key(op)] = best;
+        m[tune_key(op, "batch")] = best;
+        m[tune_key(op, "standalone")] = best_sa;
         if (!write_json(cache_json_path, m)) return SF_ERR_ARG;
     }
     return SF_OK;

@@ -65,7 +65,7 @@ template <typename T, typename D> __device__ __forceinline__ cptr<T> fresh_after
 template <int NO, int NI, bool ACC, typename T>
 __device__ __forceinline__ void apply_rows(const T *M, const T (&in)[NI], T (&out)[NO])
 {
-    constexpr int R = (NI >= 8) ? 2 : ((NI >= 4) ? 4 : 8);
+    constexpr int R = (NI >= 6) ? 1 : ((NI >= 4) ? 2 : 4);
 #pragma unroll
     for (int q0 = 0; q0 < NO; q0 += R) {
         cptr<T> m = (q0 >= 2 * R) ? fresh_after(M, out[q0 - R - 1]) : fresh(M);

@@ -74,19 +74,22 @@ struct LaunchArgs {
 
 // kernel launchers: return SF_OK, SF_ERR_UNSUPPORTED or SF_ERR_HIP
 int launch_action_q(const LaunchArgs &a);
+int launch_action_q_fast(const LaunchArgs &a);
 int launch_matrix_q(const LaunchArgs &a);
 int launch_action_vec(const LaunchArgs &a);
 int launch_matrix_vec(const LaunchArgs &a);
 int launch_action_mixed(const LaunchArgs &a);
 int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);
 
-// number of tile variants compiled for an op (autotuner search space)
-int action_variants(const LaunchArgs &a);
+// tuning keys: what = "batch" (cell groups per tile) or "standalone" (kernel variant)
+std::string tune_key(const sf_op *op, const char *what);
+int tuned_variant_of(sf_context *ctx, const sf_op *op, const char *what, int dflt);
 
 } // namespace sf
 
 struct sf_context {
     int device = 0;
+    int geometry = SF_GEOM_AFFINE;
     int *d_err = nullptr;
     std::map<std::tuple<int, int, int>, sf::TableSet> tables;
     std::map<std::string, int> tuned;

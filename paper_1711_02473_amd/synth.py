@@ -99,3 +99,20 @@ def trilinear_cells(ncells, config_id, amp=0.15):
     g = rng(config_id, 4)
     V = box_mesh(1, 1, 1, config_id).repeat(ncells, axis=0)
     return V + g.uniform(-amp, amp, V.shape)
+
+
+def device_action_inputs(ncells, n3, config_id, degree, nsets=1):
+    """Full-size action inputs drawn on the GPU (torch's Philox generator on
+    "cuda", seeded from (config_id, degree)): nsets tuples (kappa, u) of
+    [ncells][n3] FP64 tensors, kappa U[0.5, 2], u N(0, 1).  Used where the
+    host-side generators would take too long; the same seed gives the same
+    values on every run, and tests copy sampled cells back to the host."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SEED * 100 + int(config_id) * 10 + int(degree))
+    out = []
+    for _ in range(nsets):
+        kap = torch.rand((ncells, n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+        u = torch.randn((ncells, n3), generator=g, device="cuda", dtype=torch.float64)
+        out.append((kap, u))
+    return out
