@@ -109,10 +109,12 @@ const char *sf_status_string(int status);
  * SF_GEOM_AFFINE (the default): any affine cell (parallelepipeds, boxes).
  * SF_GEOM_BOX: every cell is an axis-aligned box (J diagonal); the Q_p /
  * dQ_p actions then use kernels that exploit the diagonal factor |J| G G^T
- * (two LDS tensors per cell instead of three).  Under SF_GEOM_BOX a cell
- * whose Jacobian has off-diagonal entries raises SF_FLAG_NONBOX in the
- * Laplace action and its output is unspecified (the mass action needs only
- * |det J| and stays exact on any affine cell).  The hint does not change
+ * (two LDS tensors per cell instead of three).  Under SF_GEOM_BOX the
+ * Laplace action of a cell whose Jacobian has off-diagonal entries is
+ * unspecified and raises SF_FLAG_NONBOX, except when the autotuner picked
+ * the general kernel for that op (variant 3 below), which stays exact and
+ * raises nothing; the mass action needs only |det J| and stays exact on any
+ * affine cell.  The hint does not change
  * element matrices or the H(div) / H(curl) kernels.  Returns SF_ERR_ARG for
  * an unknown value. */
 #define SF_GEOM_AFFINE 0
@@ -240,7 +242,7 @@ int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
  * unit-box cells on an internal stream, (1) the tile size of the batched
  * launch (1, 2, 4, 8 or 16 cell groups per tile; variants 0..4) and (2) for
  * FP64 / FP32 the stand-alone box-cell kernel variants (0: prefetch of the
- * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 4; 2:
+ * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 3; 2:
  * prefetch, >= 2; 3: the general three-tensor kernel that SF_GEOM_AFFINE
  * uses), and records the fastest of each in the context (and, when
  * cache_json_path is non-NULL, merges them into that JSON file, keyed by

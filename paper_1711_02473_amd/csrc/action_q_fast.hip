@@ -41,6 +41,7 @@ __global__ void __launch_bounds__(NT, MINB)
                          int *__restrict__ err)
 {
     static_assert(N == NQ, "the fast kernel assumes n Gauss points per axis");
+    static_assert(C * N * N <= NT, "one pencil per thread and stage");
     using L = Lds3<NQ>;
     constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
     constexpr int NB = (FORM == SF_LAPLACE) ? 2 : 1;
@@ -59,7 +60,6 @@ __global__ void __launch_bounds__(NT, MINB)
     T *const L1 = lds + (NB - 1) * C * CS;
 
     const int64_t ngroups = (ncells + C - 1) / C;
-    const bool has_kappa = kappa != nullptr;
     const int tid = threadIdx.x;
     // this thread's x-pencil in the HBM stages (stage 1: u; the x stage: kappa)
     const bool pen = tid < C * N2;
@@ -84,9 +84,7 @@ __global__ void __launch_bounds__(NT, MINB)
     };
     auto load_k = [&](int64_t g) {
         const int64_t gc = g * C + pc;
-        const bool ok = pen && has_kappa && gc < ncells;
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) kreg[i] = ok ? T(to_d(kappa[gc * N3 + i * N2 + pr])) : T(1);
+        ld_coeff(kappa, pen && gc < ncells, gc * N3 + pr, N2, kreg);
     };
 
     int64_t g = blockIdx.x;
@@ -102,13 +100,23 @@ __global__ void __launch_bounds__(NT, MINB)
         if (!PREF) {
             load_v(g);
             load_u(g);
+            if constexpr (FORM == SF_LAPLACE) load_k(g);
         }
 #pragma unroll
         for (int r = 0; r < VR; ++r) {
             const int t = tid + r * NT;
             if (t < 24 * C) sV[t / 24][t % 24] = vreg[r];
         }
-        if (more) load_v(gn);
+        // The next group's inputs are requested once this group has issued its last
+        // global load (vmcnt waits are in order: an earlier prefetch would make every
+        // later wait of this group wait for it too).
+        auto prefetch_next = [&] {
+            if (more) {
+                load_v(gn);
+                load_u(gn);
+                if constexpr (FORM == SF_LAPLACE) load_k(gn);
+            }
+        };
         __syncthreads(); // vertices staged; the previous group's last LDS reads are done
 
         // ---- geometry (FP64): J, det, |J| G G^T (or |J|), box test
@@ -139,17 +147,16 @@ __global__ void __launch_bounds__(NT, MINB)
                 cptr<T> W = fresh(tW);
                 const T s23 = T(sP[pc][0]) * W[pa] * W[pb];
                 const int64_t base = (cell0 + pc) * N3 + pr;
+                T k[N];
+                ld_coeff(kappa, true, base, N2, k);
 #pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    T om = s23 * W[i];
-                    if (has_kappa) om *= T(to_d(kappa[base + i * N2]));
-                    y[base + i * N2] = IO(om * ureg[i]);
-                }
+                for (int i = 0; i < N; ++i) y[base + i * N2] = IO(s23 * W[i] * k[i] * ureg[i]);
             }
-            if (more) load_u(gn);
+            prefetch_next();
             continue;
         } else {
-            // ---- stage 1 (x): u -> B_x u
+            // ---- stage 1 (x): u -> B_x u; for the Laplace form kappa is staged in L1
+            // (read back along z, then overwritten by the z stage's output)
             if (pen) {
                 if constexpr (COLL) {
                     st_pencil<0, N, S1, S2>(L0 + pc * CS, pa, pb, ureg);
@@ -158,8 +165,11 @@ __global__ void __launch_bounds__(NT, MINB)
                     mv<NQ, N>(Bt, ureg, out);
                     st_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, out);
                 }
+                if constexpr (FORM == SF_LAPLACE) st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, kreg);
             }
-            if (more) load_u(gn);
+            // kappa along this thread's y-stage pencil (one pencil per thread: C = NT / n^2)
+            T ky[NQ];
+            if constexpr (FORM == SF_LAPLACE) ld_coeff(kappa, pen && cell0 + pc < ncells, (cell0 + pc) * N3 + pa * N2 + pb, NQ, ky);
             __syncthreads();
             // ---- stage 2 (y): B_y
             if constexpr (!COLL) {
@@ -176,26 +186,24 @@ __global__ void __launch_bounds__(NT, MINB)
                 // ---- stage 3 (z): B_z, w kappa |J|, B_z^T
                 pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
                     const int64_t gc = cell0 + c;
-                    T in[N], ut[NQ], t[N];
+                    T in[N], ut[NQ], t[N], k[NQ];
+                    ld_coeff(kappa, gc < ncells, gc * N3 + (q1 * NQ + q2) * NQ, 1, k);
                     ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
                     mv<NQ, N>(Bt, in, ut);
                     cptr<T> W = fresh(tW);
                     const T w12 = T(sP[c][0]) * W[q1] * W[q2];
 #pragma unroll
-                    for (int q3 = 0; q3 < NQ; ++q3) {
-                        T om = w12 * W[q3];
-                        if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * N3 + (q1 * NQ + q2) * NQ + q3]));
-                        ut[q3] *= om;
-                    }
+                    for (int q3 = 0; q3 < NQ; ++q3) ut[q3] *= w12 * W[q3] * k[q3];
                     mtv<NQ, N>(BtT, ut, t);
                     st_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, t);
                 });
+                prefetch_next();
                 __syncthreads();
             } else {
                 // ---- box path.  stage 3 (z): u~ = B_z(.), store u~; w = Dh_z^T (w kappa P_zz Dh_z u~)
                 pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
-                    const int64_t gc = cell0 + c;
-                    T ut[NQ], gz[NQ];
+                    T ut[NQ], gz[NQ], k[NQ];
+                    ld_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, k);
                     if constexpr (COLL) {
                         ld_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, ut);
                     } else {
@@ -208,36 +216,27 @@ __global__ void __launch_bounds__(NT, MINB)
                     cptr<T> W = fresh(tW);
                     const T w12 = T(sP[c][5]) * W[q1] * W[q2];
 #pragma unroll
-                    for (int q3 = 0; q3 < NQ; ++q3) {
-                        T om = w12 * W[q3];
-                        if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * N3 + (q1 * NQ + q2) * NQ + q3]));
-                        gz[q3] *= om;
-                    }
+                    for (int q3 = 0; q3 < NQ; ++q3) gz[q3] *= w12 * W[q3] * k[q3];
                     mtv<NQ, NQ>(DhT, gz, ut);
                     st_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, ut);
                 });
                 __syncthreads();
                 // ---- stage 4 (y): w += Dh_y^T (w kappa P_yy Dh_y u~)
                 pencils<C, NQ, NQ, NT>([&](int c, int q1, int q3) {
-                    const int64_t gc = cell0 + c;
+                    const T(&k)[NQ] = ky; // this thread's only pencil
                     T ut[NQ], gy[NQ], wv[NQ];
                     ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, ut);
                     mv<NQ, NQ>(Dh, ut, gy);
                     cptr<T> W = fresh(tW);
                     const T w13 = T(sP[c][3]) * W[q1] * W[q3];
 #pragma unroll
-                    for (int q2 = 0; q2 < NQ; ++q2) {
-                        T om = w13 * W[q2];
-                        if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * N3 + (q1 * NQ + q2) * NQ + q3]));
-                        gy[q2] *= om;
-                    }
+                    for (int q2 = 0; q2 < NQ; ++q2) gy[q2] *= w13 * W[q2] * k[q2];
                     ld_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
                     mtv_acc<NQ, NQ>(DhT, gy, wv);
                     st_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
                 });
                 __syncthreads();
-                // ---- stage 5 (x): w += Dh_x^T (w kappa P_xx Dh_x u~); kappa from the prefetch registers
-                if (!PREF) load_k(g);
+                // ---- stage 5 (x): w += Dh_x^T (w kappa P_xx Dh_x u~); kappa from registers
                 if (pen) {
                     T ut[NQ], gx[NQ], wv[NQ];
                     ld_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, ut);
@@ -250,7 +249,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     mtv_acc<NQ, NQ>(DhT, gx, wv);
                     st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
                 }
-                if (more) load_k(gn);
+                prefetch_next();
                 __syncthreads();
                 // ---- backward interpolation, z then y then x; the complete w is in L1
                 if constexpr (!COLL) {
@@ -322,12 +321,12 @@ int launch_fast_v(const LaunchArgs &a, const T *tab)
 }
 
 // tile variants (autotuner search space): 0 = prefetch, >= 3 workgroups/CU;
-// 1 = no prefetch, >= 4 workgroups/CU; 2 = prefetch, >= 2 workgroups/CU
+// 1 = no prefetch, >= 3 workgroups/CU; 2 = prefetch, >= 2 workgroups/CU
 template <int N, int FORM, bool COLL, typename T, typename IO>
 int launch_fast(const LaunchArgs &a, const T *tab)
 {
     switch (a.variant) {
-    case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 4>(a, tab);
+    case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 3>(a, tab);
     case 2: return launch_fast_v<N, FORM, COLL, T, IO, true, 2>(a, tab);
     default: return launch_fast_v<N, FORM, COLL, T, IO, true, 3>(a, tab);
     }

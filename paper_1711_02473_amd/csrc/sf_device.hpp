@@ -86,6 +86,21 @@ __device__ __forceinline__ void apply_rows(const T *M, const T (&in)[NI], T (&ou
     }
 }
 
+// Coefficient values at E points (offsets off + i * stride), loaded in one
+// batch so that their memory latencies overlap; ones when kappa is absent or
+// ok is false (padding cells, idle threads).
+template <int E, typename T, typename IO>
+__device__ __forceinline__ void ld_coeff(const IO *__restrict__ kappa, bool ok, int64_t off, int stride, T (&k)[E])
+{
+    if (kappa != nullptr && ok) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) k[i] = T(to_d(kappa[off + int64_t(i) * stride]));
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) k[i] = T(1);
+    }
+}
+
 // out[q] = sum_i M[q][i] in[i] with M row-major NO x NI
 template <int NO, int NI, typename T>
 __device__ __forceinline__ void mv(const T *M, const T (&in)[NI], T (&out)[NO])

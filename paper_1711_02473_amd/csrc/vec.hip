@@ -100,7 +100,6 @@ __global__ void __launch_bounds__(NT)
     __shared__ double sG[C][13];
 
     const int64_t cell0 = int64_t(blockIdx.x) * C;
-    const bool has_kappa = kappa != nullptr;
     auto TEN = [&](int i, int c) { return lds + (i * C + c) * CS; };
 
     if (threadIdx.x < C) {
@@ -193,10 +192,11 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
             for (int t = 0; t < 6; ++t) m[t] = T(alpha * sG[c][6 + t]);
             const T sb = T(beta * sG[c][12]);
+            T kq[NQ];
+            ld_coeff(kappa, gc < ncells, gc * NQ3 + q1 * NQ + q2, NQ * NQ, kq);
 #pragma unroll
             for (int q0 = 0; q0 < NQ; ++q0) {
-                T om = W[q0] * w12;
-                if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * NQ3 + (q0 * NQ + q1) * NQ + q2]));
+                const T om = W[q0] * w12 * kq[q0];
                 T x, yv, z;
                 symmv(m, v0[q0], v1[q0], v2[q0], x, yv, z);
                 v0[q0] = om * x;
@@ -303,10 +303,11 @@ __global__ void __launch_bounds__(NT)
                 m0[t] = T(alpha * sG[c][t]);
                 m1[t] = T(beta * sG[c][6 + t]);
             }
+            T kq[NQ];
+            ld_coeff(kappa, gc < ncells, gc * NQ3 + q1 * NQ + q2, NQ * NQ, kq);
 #pragma unroll
             for (int q0 = 0; q0 < NQ; ++q0) {
-                T om = W[q0] * w12;
-                if (has_kappa && gc < ncells) om *= T(to_d(kappa[gc * NQ3 + (q0 * NQ + q1) * NQ + q2]));
+                const T om = W[q0] * w12 * kq[q0];
                 // curl^ V = (d1 V2 - d2 V1, d2 V0 - d0 V2, d0 V1 - d1 V0)
                 const T cr0 = d12[q0] - d21[q0], cr1 = d20[q0] - d02[q0], cr2 = d01[q0] - d10[q0];
                 T x, yv, z, c0, c1, c2;

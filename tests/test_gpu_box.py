@@ -100,13 +100,20 @@ def test_box_action_fp32(ctx, tmp_path, prec, io, tol, p):
         assert rel_l2(y, ref) <= tol, (v, rel_l2(y, ref))
 
 
-def test_box_mode_flags_non_box_cells(ctx):
-    """Under SF_GEOM_BOX, sheared cells raise SF_FLAG_NONBOX; boxes raise nothing;
-    a collapsed box raises SF_FLAG_DETJ."""
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_box_mode_flags_non_box_cells(ctx, tmp_path, variant):
+    """Under SF_GEOM_BOX, sheared cells raise SF_FLAG_NONBOX in the box-cell kernels
+    (the general kernel, variant 3, computes them exactly instead); boxes raise
+    nothing; a collapsed box raises SF_FLAG_DETJ."""
     op = sf.make_op("Q", 3, "LAPLACE")
+    force_variant(ctx, op, variant, tmp_path)
     u = synth.dof_vector(16, 64, 14)
-    _, f = launch(ctx, op, synth.affine_cells(16, 14), None, u)
-    assert f & sf.SF_FLAG_NONBOX
+    aff = synth.affine_cells(16, 14)
+    y, f = launch(ctx, op, aff, None, u)
+    if variant == 3:
+        assert f == 0 and rel_l2(y, oracle.action("Q", 3, "LAPLACE", aff, u)) <= TOL64
+    else:
+        assert f & sf.SF_FLAG_NONBOX
     boxes = synth.box_mesh(2, 2, 4, 14)
     _, f = launch(ctx, op, boxes, None, u)
     assert f == 0
