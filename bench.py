@@ -57,12 +57,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--mixed-degrees", default="4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
     ap.add_argument("--no-tune", action="store_true", help="skip sf_autotune (library defaults)")
+    ap.add_argument("--legs", default="mass,vec,matrix,batch",
+                    help="side measurements beside the headline: mass (Q_p mass action, 64^3), vec (NCF/NCE "
+                         "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
+                         "launch); '' = none")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the action is cell-local; see DESIGN.md "
-              "for how it shards); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: measures one GPU only (the action is cell-local, so more GPUs would each "
+              "take a share of the cells); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -147,6 +151,18 @@ def main():
         mixed = mixed_leg(sf, ctx, V, bufs, ncells, [int(x) for x in args.mixed_degrees.split(",")], ms, glob,
                           max(3, args.steps // 2), stream)
 
+    legs = [x for x in args.legs.split(",") if x]
+    copy_gbs = measured_copy_gbs()
+    side = {}
+    if "mass" in legs:
+        side["mass_action"] = mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, args.steps, stream)
+    if "vec" in legs:
+        side["vec_action"] = vec_leg(sf, ctx, args.steps, stream)
+    if "matrix" in legs:
+        side["element_matrix"] = matrix_leg(sf, ctx, V, degrees, stream)
+    if "batch" in legs:
+        side["batched"] = batch_leg(sf, ctx, stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(degrees, bufs, V, glob, ncells, args.cpu_seconds)
@@ -161,6 +177,8 @@ def main():
                    % ",".join(map(str, degrees)), "ncells": ncells, "degrees": degrees},
         "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p, "mixed_precision": mixed,
         "tuned_variants": {k.split("|", 1)[1]: v for k, v in tuned.items()},
+        "measured_copy_gbs": round(copy_gbs, 1), "frac_vs_measured_copy": round(achieved / copy_gbs, 4),
+        "legs": side,
     }
     if args.calib_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -171,6 +189,193 @@ def main():
         out["calib_copy_bytes"] = 1 << 30
     print(json.dumps(out))
     ctx.close()
+
+
+def timed(fn, reps, stream):
+    """Mean milliseconds of fn() over reps launches, bracketed by HIP events on `stream`."""
+    import torch
+
+    ts = []
+    for it in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn(it)
+        b.record(stream)
+        ts.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ts]))
+
+
+def measured_copy_gbs():
+    """Device-to-device copy of 1 GiB (read + write = 2 GiB of traffic): the
+    practical HBM rate next to the 8 TB/s specification."""
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = timed(lambda it: b.copy_(a), 5, torch.cuda.current_stream())
+    del a, b
+    return 2.0 * (1 << 30) / (ms / 1e3) / 1e9
+
+
+def mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, reps, stream):
+    """Q_p mass action (kappa per Gauss point) on the same 64^3 box mesh, FP64;
+    HBM-bound at every p: bytes = 24 n^3 + 192 per cell."""
+    import torch
+
+    out = {}
+    for p in degrees:
+        op = sf.make_op("Q", p, "MASS")
+        sets = bufs[p]
+        y = torch.empty_like(sets[0][1])
+        sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], y, stream)
+        ms = timed(lambda it: sf.assemble_action(ctx, op, ncells, V, sets[it % len(sets)][0], sets[it % len(sets)][1],
+                                                 y, stream), reps, stream)
+        gbs = action_bytes_per_cell(p) * ncells / (ms / 1e3) / 1e9
+        out[str(p)] = {"ms": round(ms, 4), "gdofs_global": round(glob[p] / (ms / 1e3) / 1e9, 3),
+                       "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+    assert sf.sf_check_errors(ctx) == 0
+    return out
+
+
+def vec_leg(sf, ctx, reps, stream, n1=48):
+    """H(div) NCF_k (alpha mass + beta div-div) and H(curl) NCE_k (alpha mass +
+    beta curl-curl) actions, k = 1..6, alpha = beta = 1, kappa = 1, on n1^3 box
+    cells with FP64 and FP32 storage.  Bytes per cell: u + y + 192 (vertices)."""
+    import torch
+
+    from paper_1711_02473_amd import synth
+
+    ncells = n1 ** 3
+    V = torch.from_numpy(synth.box_mesh(n1, n1, n1, 4)).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(synth.SEED * 100 + 40)
+    out = {}
+    for fam, form in (("NCF", "HDIV"), ("NCE", "HCURL")):
+        for io, tdt, isz in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            for k in range(1, 7):
+                op = sf.make_op(fam, k, form, io=io)
+                nd, _ = sf.sf_element_dims(op)
+                u = torch.randn((2, ncells, nd), generator=g, device="cuda", dtype=torch.float64).to(tdt)
+                y = torch.empty((ncells, nd), device="cuda", dtype=tdt)
+                sf.assemble_action(ctx, op, ncells, V, None, u[0], y, stream)
+                ms = timed(lambda it: sf.assemble_action(ctx, op, ncells, V, None, u[it % 2], y, stream), reps, stream)
+                gbs = (2 * nd * isz + 192) * ncells / (ms / 1e3) / 1e9
+                out["%s%d_%s" % (fam, k, io)] = {"ms": round(ms, 4), "gdofs_local": round(ncells * nd / (ms / 1e3) / 1e9, 3),
+                                                 "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+                del u, y
+    assert sf.sf_check_errors(ctx) == 0
+    return out
+
+
+def matrix_leg(sf, ctx, V, degrees, stream, budget_bytes=4 << 30):
+    """Q_p Laplace element matrices (kappa per Gauss point), FP64, on the first
+    cells of the 64^3 mesh: as many cells as fit in a 4 GiB output.  Bound by
+    the HBM writes of the matrices: bytes = 8 n^6 + 8 n^3 + 192 per cell."""
+    import torch
+
+    out = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(synth_seed() + 50)
+    for p in degrees:
+        n3 = (p + 1) ** 3
+        nc = int(min(V.shape[0], budget_bytes // (8 * n3 * n3)))
+        kap = torch.rand((nc, n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+        A = torch.empty((nc, n3, n3), device="cuda", dtype=torch.float64)
+        op = sf.make_op("Q", p, "LAPLACE")
+        sf.assemble_element_matrix(ctx, op, nc, V, kap, A, stream)
+        ms = timed(lambda it: sf.assemble_element_matrix(ctx, op, nc, V, kap, A, stream), 5, stream)
+        bts = (8 * n3 * n3 + 8 * n3 + 192) * nc
+        out[str(p)] = {"cells": nc, "ms": round(ms, 4), "cells_per_s": round(nc / (ms / 1e3), 1),
+                       "hbm_gbs": round(bts / (ms / 1e3) / 1e9, 1),
+                       "hbm_frac": round(bts / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        del kap, A
+    assert sf.sf_check_errors(ctx) == 0
+    return out
+
+
+def synth_seed():
+    from paper_1711_02473_amd import synth
+    return synth.SEED * 100
+
+
+def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
+    """The batched workload: 2048 box meshes of n_m^3 cells (n_m uniform in
+    4..16) and degree p_m (uniform in 2..8), Laplace action with kappa per Gauss
+    point in one persistent launch replayed from a hipGraph, FP64 and with
+    BF16 / BF16 x3 contractions (error against the FP64 batch), then the same
+    meshes' element matrices (FP64) together with the FP64 actions in one
+    launch, matrices written into a per-degree arena of 2 GiB cycled per job."""
+    import torch
+
+    from paper_1711_02473_amd import synth
+
+    wl = synth.batched_workload(nmeshes)
+    verts = [synth.batch_mesh(m, n) for m, (n, p) in enumerate(wl)]
+    ncell = [n ** 3 for n, p in wl]
+    off = np.concatenate([[0], np.cumsum(ncell)])
+    V = torch.from_numpy(np.concatenate(verts)).cuda()
+    del verts
+    degs = sorted(set(p for n, p in wl))
+    # per degree: one slab of kappa, u, y holding that degree's meshes back to back
+    slab_off, cnt = {}, {p: 0 for p in degs}
+    for m, (n, p) in enumerate(wl):
+        slab_off[m] = cnt[p]
+        cnt[p] += n ** 3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(synth.SEED * 100 + 55)
+    kap, u, y, yb = {}, {}, {}, {}
+    for p in degs:
+        n3 = (p + 1) ** 3
+        kap[p] = torch.rand((cnt[p], n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+        u[p] = torch.randn((cnt[p], n3), generator=g, device="cuda", dtype=torch.float64)
+        y[p] = torch.empty_like(u[p])
+        yb[p] = torch.empty_like(u[p])
+    arena = {p: torch.empty(arena_bytes // 8, device="cuda", dtype=torch.float64) for p in degs}
+    esz = 8
+
+    def jobs(precision, ybuf, matrices=False, actions=True):
+        js = []
+        for m, (n, p) in enumerate(wl):
+            n3 = (p + 1) ** 3
+            vp = V.data_ptr() + int(off[m]) * 24 * esz
+            kp = kap[p].data_ptr() + slab_off[m] * n3 * esz
+            if actions:
+                js.append(sf.make_job(sf.make_op("Q", p, "LAPLACE", precision=precision), ncell[m], vp, kp,
+                                      u[p].data_ptr() + slab_off[m] * n3 * esz,
+                                      ybuf[p].data_ptr() + slab_off[m] * n3 * esz))
+            if matrices:
+                js.append(sf.make_job(sf.make_op("Q", p, "LAPLACE"), ncell[m], vp, kp, A=arena[p],
+                                      A_arena_cells=max(1, arena_bytes // (esz * n3 * n3))))
+        return js
+
+    loc = sum(ncell[m] * (p + 1) ** 3 for m, (n, p) in enumerate(wl))
+    act_bytes = sum(ncell[m] * (24 * (p + 1) ** 3 + 192) for m, (n, p) in enumerate(wl))
+    mat_bytes = sum(ncell[m] * (8 * (p + 1) ** 6 + 8 * (p + 1) ** 3 + 192) for m, (n, p) in enumerate(wl))
+    out = {"meshes": nmeshes, "cells": int(off[-1]), "local_dofs": int(loc)}
+    for prec, yy in (("fp64", y), ("bf16", yb), ("bf16x3", yb)):
+        b = sf.Batch(ctx, jobs(prec, yy))
+        b.launch(stream)
+        ms = timed(lambda it: b.launch(stream), 5, stream)
+        row = {"ms": round(ms, 4), "gdofs_local": round(loc / (ms / 1e3) / 1e9, 3),
+               "hbm_gbs": round(act_bytes / (ms / 1e3) / 1e9, 1), "tiles_workgroups": list(b.info())}
+        if prec != "fp64":
+            num = sum(float(torch.linalg.vector_norm(yb[p] - y[p]) ** 2) for p in degs)
+            den = sum(float(torch.linalg.vector_norm(y[p]) ** 2) for p in degs)
+            row["rel_l2_vs_fp64_gpu"] = float("%.3e" % (num / den) ** 0.5)
+        out["action_" + prec] = row
+        b.close()
+    b = sf.Batch(ctx, jobs("fp64", y, matrices=True, actions=True))
+    b.launch(stream)
+    ms = timed(lambda it: b.launch(stream), 3, stream)
+    out["action_and_matrix_fp64"] = {"ms": round(ms, 3), "hbm_gbs": round((act_bytes + mat_bytes) / (ms / 1e3) / 1e9, 1),
+                                     "hbm_frac": round((act_bytes + mat_bytes) / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                                     "matrix_bytes": int(mat_bytes), "tiles_workgroups": list(b.info())}
+    b.close()
+    assert sf.sf_check_errors(ctx) == 0
+    del kap, u, y, yb, arena
+    return out
 
 
 def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):

@@ -75,6 +75,14 @@ def batched_workload(nmeshes=2048, config_id=5, nmin=4, nmax=16, pmin=2, pmax=8)
     return [(int(a), int(b)) for a, b in zip(ns, ps)]
 
 
+def batch_mesh(m, n, config_id=5):
+    """Mesh m of the batched workload: an n x n x n box grid whose spacings are
+    drawn from default_rng([SEED, config_id, 0, m]), U[0.5, 1.5]."""
+    g = np.random.default_rng([SEED, int(config_id), 0, int(m)])
+    cum = lambda h: np.concatenate([[0.0], np.cumsum(h)])
+    return grid_vertices(cum(g.uniform(0.5, 1.5, n)), cum(g.uniform(0.5, 1.5, n)), cum(g.uniform(0.5, 1.5, n)))
+
+
 def affine_cells(ncells, config_id, shear=0.3):
     """Parallelepiped cells x = x0 + J xi with J = diag(U[0.5,1.5]) + U[-shear, shear]
     off the diagonal (det J > 0 for shear <= 0.3)."""
