@@ -379,9 +379,10 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
 
 
 def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
-    """Laplace action with MFMA contractions (BF16 / FP16 single term, BF16 x3
-    split) against the FP64 GPU path on the same inputs (FP64 storage): rate,
-    speed-up and relative L2 difference over the whole output."""
+    """Laplace action with lower-precision contractions (FP32 on the vector
+    ALUs; BF16 / FP16 single term and BF16 x3 split on MFMA), geometry and
+    pointwise factors in FP64, against the FP64 GPU path on the same inputs
+    (FP64 storage): rate, speed-up and relative L2 difference."""
     import torch
 
     out = {}
@@ -392,7 +393,7 @@ def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
         ref = torch.empty_like(y)
         sf.assemble_action(ctx, sf.make_op("Q", p, "LAPLACE"), ncells, V, kap, u, ref, stream)
         row = {}
-        for mode in ("bf16", "fp16", "bf16x3"):
+        for mode in ("fp32", "bf16", "fp16", "bf16x3"):
             op = sf.make_op("Q", p, "LAPLACE", precision=mode)
             ym = torch.empty_like(y)
             sf.assemble_action(ctx, op, ncells, V, kap, u, ym, stream)

@@ -43,6 +43,10 @@ template <typename T> __device__ __forceinline__ cptr<T> fresh(const T *p)
     return (cptr<T>)v;
 }
 
+// fused multiply-add in the operands' own precision
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ double to_d(double x) { return x; }
 __device__ __forceinline__ double to_d(float x) { return static_cast<double>(x); }
 template <typename T> __device__ __forceinline__ T conv(double x) { return static_cast<T>(x); }
@@ -80,7 +84,7 @@ __device__ __forceinline__ void apply_rows(const T *M, const T (&in)[NI], T (&ou
                 i0 = 1;
             }
 #pragma unroll
-            for (int i = i0; i < NI; ++i) acc = __builtin_fma(m[q * NI + i], in[i], acc);
+            for (int i = i0; i < NI; ++i) acc = fmadd(T(m[q * NI + i]), in[i], acc);
             out[q] = acc;
         }
     }
