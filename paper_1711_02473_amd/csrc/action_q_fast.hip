@@ -47,10 +47,11 @@ __global__ void __launch_bounds__(NT, MINB)
     constexpr int NB = (FORM == SF_LAPLACE) ? 2 : 1;
     constexpr TabLayout TL(N, 0, NQ);
     constexpr int N2 = N * N, N3 = N2 * N;
-    const T *const Bt = tab + TL.B0();
-    const T *const BtT = tab + TL.B0T();
-    const T *const Dh = tab + TL.Dh();
-    const T *const DhT = tab + TL.DhT();
+    // even-odd packed tables: B, B^T centrosymmetric, Dh, Dh^T skew-centrosymmetric
+    const T *const Bt = tab + TL.BEO();
+    const T *const BtT = tab + TL.BTEO();
+    const T *const Dh = tab + TL.DhEO();
+    const T *const DhT = tab + TL.DhTEO();
     const T *const tW = tab + TL.W();
 
     __shared__ T lds[NB * C * CS];
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     st_pencil<0, N, S1, S2>(L0 + pc * CS, pa, pb, ureg);
                 } else {
                     T out[NQ];
-                    mv<NQ, N>(Bt, ureg, out);
+                    apply_eo<N, false, false>(Bt, ureg, out);
                     st_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, out);
                 }
                 if constexpr (FORM == SF_LAPLACE) st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, kreg);
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(NT, MINB)
                 pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
                     T in[N], out[NQ];
                     ld_pencil<1, N, S1, S2>(L0 + c * CS, q1, i3, in);
-                    mv<NQ, N>(Bt, in, out);
+                    apply_eo<N, false, false>(Bt, in, out);
                     st_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, i3, out);
                 });
                 __syncthreads();
@@ -189,12 +190,12 @@ __global__ void __launch_bounds__(NT, MINB)
                     T in[N], ut[NQ], t[N], k[NQ];
                     ld_coeff(kappa, gc < ncells, gc * N3 + (q1 * NQ + q2) * NQ, 1, k);
                     ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
-                    mv<NQ, N>(Bt, in, ut);
+                    apply_eo<N, false, false>(Bt, in, ut);
                     cptr<T> W = fresh(tW);
                     const T w12 = T(sP[c][0]) * W[q1] * W[q2];
 #pragma unroll
                     for (int q3 = 0; q3 < NQ; ++q3) ut[q3] *= w12 * W[q3] * k[q3];
-                    mtv<NQ, N>(BtT, ut, t);
+                    apply_eo<N, false, false>(BtT, ut, t);
                     st_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, t);
                 });
                 prefetch_next();
@@ -209,15 +210,15 @@ __global__ void __launch_bounds__(NT, MINB)
                     } else {
                         T in[N];
                         ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
-                        mv<NQ, N>(Bt, in, ut);
+                        apply_eo<N, false, false>(Bt, in, ut);
                         st_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, ut);
                     }
-                    mv<NQ, NQ>(Dh, ut, gz);
+                    apply_eo<N, true, false>(Dh, ut, gz);
                     cptr<T> W = fresh(tW);
                     const T w12 = T(sP[c][5]) * W[q1] * W[q2];
 #pragma unroll
                     for (int q3 = 0; q3 < NQ; ++q3) gz[q3] *= w12 * W[q3] * k[q3];
-                    mtv<NQ, NQ>(DhT, gz, ut);
+                    apply_eo<N, true, false>(DhT, gz, ut);
                     st_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, ut);
                 });
                 __syncthreads();
@@ -226,13 +227,13 @@ __global__ void __launch_bounds__(NT, MINB)
                     const T(&k)[NQ] = ky; // this thread's only pencil
                     T ut[NQ], gy[NQ], wv[NQ];
                     ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, ut);
-                    mv<NQ, NQ>(Dh, ut, gy);
+                    apply_eo<N, true, false>(Dh, ut, gy);
                     cptr<T> W = fresh(tW);
                     const T w13 = T(sP[c][3]) * W[q1] * W[q3];
 #pragma unroll
                     for (int q2 = 0; q2 < NQ; ++q2) gy[q2] *= w13 * W[q2] * k[q2];
                     ld_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
-                    mtv_acc<NQ, NQ>(DhT, gy, wv);
+                    apply_eo<N, true, true>(DhT, gy, wv);
                     st_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
                 });
                 __syncthreads();
@@ -240,13 +241,13 @@ __global__ void __launch_bounds__(NT, MINB)
                 if (pen) {
                     T ut[NQ], gx[NQ], wv[NQ];
                     ld_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, ut);
-                    mv<NQ, NQ>(Dh, ut, gx);
+                    apply_eo<N, true, false>(Dh, ut, gx);
                     cptr<T> W = fresh(tW);
                     const T w23 = T(sP[pc][0]) * W[pa] * W[pb];
 #pragma unroll
                     for (int q1 = 0; q1 < NQ; ++q1) gx[q1] *= w23 * W[q1] * kreg[q1];
                     ld_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
-                    mtv_acc<NQ, NQ>(DhT, gx, wv);
+                    apply_eo<N, true, true>(DhT, gx, wv);
                     st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
                 }
                 prefetch_next();
@@ -256,7 +257,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
                         T in[NQ], t[N];
                         ld_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, in);
-                        mtv<NQ, N>(BtT, in, t);
+                        apply_eo<N, false, false>(BtT, in, t);
                         st_pencil<2, N, S1, S2>(L1 + c * CS, q1, q2, t);
                     });
                     __syncthreads();
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(NT, MINB)
                 pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
                     T in[NQ], out[N];
                     ld_pencil<1, NQ, S1, S2>(LB + c * CS, q1, i3, in);
-                    mtv<NQ, N>(BtT, in, out);
+                    apply_eo<N, false, false>(BtT, in, out);
                     st_pencil<1, N, S1, S2>(LB + c * CS, q1, i3, out);
                 });
                 __syncthreads();
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(NT, MINB)
 #pragma unroll
                     for (int i = 0; i < N; ++i) out[i] = in[i];
                 } else {
-                    mtv<NQ, N>(BtT, in, out);
+                    apply_eo<N, false, false>(BtT, in, out);
                 }
                 IO *yo = y + (cell0 + pc) * N3 + pr;
 #pragma unroll

@@ -2,11 +2,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdio>
-#include <string>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "sf_internal.hpp"
@@ -110,6 +110,31 @@ std::vector<uint16_t> mixed_planes(const std::vector<double> &h, const TabLayout
     return m;
 }
 
+// Even-odd packing of a square n x n row-major matrix M at h[src] with
+// M[n-1-q][n-1-i] = s M[q][i] (s = -1 when skew): for each row q < n/2 the
+// entries (M[q][i] + M[q][n-1-i]) / 2 for i < n/2, M[q][n/2] when n is odd,
+// then (M[q][i] - M[q][n-1-i]) / 2 for i < n/2; for odd n the middle row
+// M[n/2][0..n/2] follows.  Returns false if M lacks the symmetry.
+bool pack_eo(std::vector<double> &h, int src, int dst, int n, bool skew)
+{
+    const double s = skew ? -1.0 : 1.0;
+    double scale = 0.0;
+    for (int k = 0; k < n * n; ++k) scale = std::max(scale, std::fabs(h[src + k]));
+    for (int q = 0; q < n; ++q)
+        for (int i = 0; i < n; ++i)
+            if (std::fabs(h[src + (n - 1 - q) * n + (n - 1 - i)] - s * h[src + q * n + i]) > 1e-12 * scale) return false;
+    const int hh = n / 2, od = n % 2, rw = 2 * hh + od;
+    auto M = [&](int q, int i) { return h[src + q * n + i]; };
+    for (int q = 0; q < hh; ++q) {
+        for (int i = 0; i < hh; ++i) h[dst + q * rw + i] = 0.5 * (M(q, i) + M(q, n - 1 - i));
+        if (od) h[dst + q * rw + hh] = M(q, hh);
+        for (int i = 0; i < hh; ++i) h[dst + q * rw + hh + od + i] = 0.5 * (M(q, i) - M(q, n - 1 - i));
+    }
+    if (od)
+        for (int i = 0; i <= hh; ++i) h[dst + hh * rw + i] = M(hh, i);
+    return true;
+}
+
 int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out)
 {
     auto key = std::make_tuple(int(op->family), int(op->degree), d.nq1);
@@ -141,6 +166,13 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
     transpose(L.B1(), L.B1T(), d.nq1, d.n1);
     transpose(L.D1(), L.D1T(), d.nq1, d.n1);
     transpose(L.Dh(), L.DhT(), d.nq1, d.nq1);
+    if (d.n0 == d.nq1) {
+        // node and point sets are symmetric about 1/2, so B and B^T are centrosymmetric and
+        // Dh, Dh^T skew-centrosymmetric; pack their even-odd forms (see apply_eo)
+        const bool ok = pack_eo(h, L.B0(), L.BEO(), d.nq1, false) && pack_eo(h, L.B0T(), L.BTEO(), d.nq1, false) &&
+                        pack_eo(h, L.Dh(), L.DhEO(), d.nq1, true) && pack_eo(h, L.DhT(), L.DhTEO(), d.nq1, true);
+        if (!ok) return SF_ERR_UNSUPPORTED;
+    }
 
     TableSet ts;
     ts.len = L.size();

@@ -105,6 +105,61 @@ __device__ __forceinline__ void ld_coeff(const IO *__restrict__ kappa, bool ok, 
     }
 }
 
+// Even-odd application of a square N x N matrix with M[N-1-q][N-1-i] =
+// s M[q][i] (s = +1, or -1 when SKEW): with x_e[i] = x[i] + x[N-1-i] and
+// x_o[i] = x[i] - x[N-1-i] (i < h = N/2), rows q < h give E = sum Me x_e
+// (+ M[q][h] x[h] for odd N) and O = sum Mo x_o, and y[q] = E + O,
+// y[N-1-q] = E - O (SKEW: O - E); for odd N the middle row uses x_e (x_o
+// when SKEW).  About (N^2 + N) / 2 + 2N operations instead of N^2.  The packed
+// layout of M (host-built) is documented with pack_eo.  ACC adds into y.
+template <int N, bool SKEW, bool ACC, typename T>
+__device__ __forceinline__ void apply_eo(const T *M, const T (&x)[N], T (&y)[N])
+{
+    constexpr int h = N / 2, od = N % 2, RW = 2 * h + od;
+    static_assert(h >= 1, "N >= 2");
+    T xe[h], xo[h];
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+        xe[i] = x[i] + x[N - 1 - i];
+        xo[i] = x[i] - x[N - 1 - i];
+    }
+#pragma unroll
+    for (int q = 0; q < h; ++q) {
+        cptr<T> m = (q >= 2) ? fresh_after(M, y[q - 2]) : fresh(M);
+        T e = T(m[q * RW]) * xe[0];
+#pragma unroll
+        for (int i = 1; i < h; ++i) e = fmadd(T(m[q * RW + i]), xe[i], e);
+        if constexpr (od) e = fmadd(T(m[q * RW + h]), x[h], e);
+        T o = T(m[q * RW + h + od]) * xo[0];
+#pragma unroll
+        for (int i = 1; i < h; ++i) o = fmadd(T(m[q * RW + h + od + i]), xo[i], o);
+        const T lo = e + o, hi = SKEW ? o - e : e - o;
+        if constexpr (ACC) {
+            y[q] += lo;
+            y[N - 1 - q] += hi;
+        } else {
+            y[q] = lo;
+            y[N - 1 - q] = hi;
+        }
+    }
+    if constexpr (od) {
+        cptr<T> m = fresh_after(M, y[h - 1]);
+        T a;
+        if constexpr (SKEW) {
+            a = T(m[h * RW]) * xo[0];
+#pragma unroll
+            for (int i = 1; i < h; ++i) a = fmadd(T(m[h * RW + i]), xo[i], a);
+        } else {
+            a = T(m[h * RW]) * xe[0];
+#pragma unroll
+            for (int i = 1; i < h; ++i) a = fmadd(T(m[h * RW + i]), xe[i], a);
+            a = fmadd(T(m[h * RW + h]), x[h], a);
+        }
+        if constexpr (ACC) y[h] += a;
+        else y[h] = a;
+    }
+}
+
 // out[q] = sum_i M[q][i] in[i] with M row-major NO x NI
 template <int NO, int NI, typename T>
 __device__ __forceinline__ void mv(const T *M, const T (&in)[NI], T (&out)[NO])

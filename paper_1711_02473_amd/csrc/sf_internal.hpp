@@ -43,7 +43,16 @@ struct TabLayout {
     __host__ __device__ constexpr int B1T() const { return D0T() + nq * n0; }
     __host__ __device__ constexpr int D1T() const { return B1T() + nq * n1; }
     __host__ __device__ constexpr int DhT() const { return D1T() + nq * n1; }
-    __host__ __device__ constexpr int size() const { return DhT() + nq * nq; }
+    // even-odd packed forms of the square matrices B0 (when n0 == nq), B0^T, Dh, Dh^T
+    __host__ __device__ static constexpr int eo_len(int n)
+    {
+        return (n / 2) * (2 * (n / 2) + n % 2) + (n % 2) * (n / 2 + 1);
+    }
+    __host__ __device__ constexpr int BEO() const { return DhT() + nq * nq; }
+    __host__ __device__ constexpr int BTEO() const { return BEO() + eo_len(nq); }
+    __host__ __device__ constexpr int DhEO() const { return BTEO() + eo_len(nq); }
+    __host__ __device__ constexpr int DhTEO() const { return DhEO() + eo_len(nq); }
+    __host__ __device__ constexpr int size() const { return DhTEO() + eo_len(nq); }
 };
 
 // Tables split into three bf16 terms (hi, mid, lo) and single fp16 / bf16
