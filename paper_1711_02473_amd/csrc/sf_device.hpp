@@ -160,6 +160,29 @@ __device__ __forceinline__ void apply_eo(const T *M, const T (&x)[N], T (&y)[N])
     }
 }
 
+// This thread's share (slots t = threadIdx.x + k NT < C E) of a group's
+// cell-major rows of E entries, loaded in one batch so that the loads
+// overlap; `fill` for padding cells, empty slots or a NULL array.
+template <int C, int E, int NT, typename T, typename IO>
+__device__ __forceinline__ void ld_rows(const IO *__restrict__ src, int64_t cell0, int64_t ncells, T fill,
+                                        T (&v)[(C * E + NT - 1) / NT])
+{
+    constexpr int K = (C * E + NT - 1) / NT;
+    if (src == nullptr) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = fill;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int t = threadIdx.x + k * NT;
+        const int c = t / E;
+        const bool ok = t < C * E && cell0 + c < ncells;
+        const IO x = src[ok ? (cell0 + c) * E + (t - c * E) : 0];
+        v[k] = ok ? T(to_d(x)) : fill;
+    }
+}
+
 // out[q] = sum_i M[q][i] in[i] with M row-major NO x NI
 template <int NO, int NI, typename T>
 __device__ __forceinline__ void mv(const T *M, const T (&in)[NI], T (&out)[NO])
@@ -206,6 +229,23 @@ template <int C, int P0, int P1, int NT, typename F> __device__ __forceinline__ 
 {
     constexpr int NP = P0 * P1;
     for (int t = threadIdx.x; t < C * NP; t += NT) {
+        const int c = t / NP;
+        const int r = t - c * NP;
+        const int a = r / P1;
+        const int b = r - a * P1;
+        f(c, a, b);
+    }
+}
+
+// Pencils of one of several independent stages that run side by side (the
+// blocks of an enriched element): threads [lo, lo + span) take this stage's
+// C*P0*P1 pencils, the other threads skip it.
+template <int C, int P0, int P1, typename F> __device__ __forceinline__ void pencils_part(int lo, int span, F &&f)
+{
+    constexpr int NP = P0 * P1;
+    const int t0 = int(threadIdx.x) - lo;
+    if (t0 < 0 || t0 >= span) return;
+    for (int t = t0; t < C * NP; t += span) {
         const int c = t / NP;
         const int r = t - c * NP;
         const int a = r / P1;

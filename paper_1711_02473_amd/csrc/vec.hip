@@ -88,6 +88,9 @@ __global__ void __launch_bounds__(NT)
     // tensors per cell: NCF: V0 V1 V2 D0 D1 D2; NCE: V0 V1 V2 and dV_c along its two P axes
     constexpr int NTEN = (FAM == SF_NCF) ? 6 : 9;
     constexpr TabLayout TL(NP, ND, NQ);
+    // the three blocks' contractions run side by side, one third of the threads each
+    static_assert(NT % 3 == 0, "three equal thread ranges");
+    constexpr int SPAN = NT / 3;
     const T *const BP = tab + TL.B0();
     const T *const DP = tab + TL.D0();
     const T *const BD = tab + TL.B1();
@@ -101,6 +104,10 @@ __global__ void __launch_bounds__(NT)
 
     const int64_t cell0 = int64_t(blockIdx.x) * C;
     auto TEN = [&](int i, int c) { return lds + (i * C + c) * CS; };
+    // the group's local DOFs, requested before the geometry work
+    constexpr int KU = (C * NF + NT - 1) / NT;
+    T uv[KU];
+    ld_rows<C, NF, NT>(u, cell0, ncells, T(0), uv);
 
     if (threadIdx.x < C) {
         const int64_t gc = cell0 + threadIdx.x;
@@ -117,10 +124,12 @@ __global__ void __launch_bounds__(NT)
         sG[threadIdx.x][12] = rS;
     }
     // ---- stage the local DOFs into the three block tensors (coalesced over the flat index)
-    for (int t = threadIdx.x; t < C * NF; t += NT) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+        const int t = threadIdx.x + k * NT;
+        if (t >= C * NF) break;
         const int c = t / NF, d = t - c * NF;
-        const int64_t gc = cell0 + c;
-        const T val = gc < ncells ? T(to_d(u[gc * NF + d])) : T(0);
+        const T val = uv[k];
         int blk, r;
         if (d < E::off(1)) { blk = 0; r = d; }
         else if (d < E::off(2)) { blk = 1; r = d - E::off(1); }
@@ -140,7 +149,7 @@ __global__ void __launch_bounds__(NT)
         constexpr int E0 = decltype(e0)::value, E1 = decltype(e1)::value, E2 = decltype(e2)::value;
         constexpr int EI = AX == 0 ? E0 : (AX == 1 ? E1 : E2);
         using O = Others<AX, E0, E1, E2>;
-        pencils<C, O::P0, O::P1, NT>([&](int c, int a, int b) {
+        pencils_part<C, O::P0, O::P1>((CB) * SPAN, SPAN, [&](int c, int a, int b) {
             T in[EI], o1[NQ];
             ld_pencil<AX, EI, S1, S2>(TEN(CB, c), a, b, in);
             if (M2p) {
@@ -213,7 +222,7 @@ __global__ void __launch_bounds__(NT)
         // backward B1: axis c, T = BP^T v + DP^T s  (NQ -> NP), in place
         auto bwd_c = [&](auto cblk) {
             constexpr int CB = decltype(cblk)::value;
-            pencils<C, NQ, NQ, NT>([&](int c, int a, int b) {
+            pencils_part<C, NQ, NQ>((CB) * SPAN, SPAN, [&](int c, int a, int b) {
                 T v[NQ], s[NQ], o[NP];
                 ld_pencil<CB, NQ, S1, S2>(TEN(CB, c), a, b, v);
                 ld_pencil<CB, NQ, S1, S2>(TEN(3, c), a, b, s);
@@ -231,7 +240,7 @@ __global__ void __launch_bounds__(NT)
             constexpr int CB = decltype(cblk)::value, AX = decltype(ax)::value;
             constexpr int E0 = decltype(e0)::value, E1 = decltype(e1)::value, E2 = decltype(e2)::value;
             using O = Others<AX, E0, E1, E2>;
-            pencils<C, O::P0, O::P1, NT>([&](int c, int a, int b) {
+            pencils_part<C, O::P0, O::P1>((CB) * SPAN, SPAN, [&](int c, int a, int b) {
                 T v[NQ], o[ND];
                 ld_pencil<AX, NQ, S1, S2>(TEN(CB, c), a, b, v);
                 mtv<NQ, ND>(BDT, v, o);
@@ -269,7 +278,7 @@ __global__ void __launch_bounds__(NT)
                 constexpr int E0 = decltype(e0)::value, E1 = decltype(e1)::value, E2 = decltype(e2)::value;
                 constexpr int EI = AX == 0 ? E0 : (AX == 1 ? E1 : E2);
                 using O = Others<AX, E0, E1, E2>;
-                pencils<C, O::P0, O::P1, NT>([&](int c, int a, int b) {
+                pencils_part<C, O::P0, O::P1>((ten - 3) * SPAN, SPAN, [&](int c, int a, int b) {
                     T in[EI], o[NQ];
                     ld_pencil<AX, EI, S1, S2>(TEN(ten, c), a, b, in);
                     mv<NQ, EI>(BP, in, o);
@@ -341,7 +350,7 @@ __global__ void __launch_bounds__(NT)
         // backward B1: second P axis o1: V <- BP^T V + DP^T r_o1 ; r_o0 <- BP^T r_o0   (NQ -> NP)
         auto bwd_o1 = [&](auto cblk, auto ax) {
             constexpr int CB = decltype(cblk)::value, AX = decltype(ax)::value;
-            pencils<C, NQ, NQ, NT>([&](int c, int a, int b) {
+            pencils_part<C, NQ, NQ>((CB) * SPAN, SPAN, [&](int c, int a, int b) {
                 T v[NQ], r1[NQ], r0[NQ], o[NP], o0[NP];
                 ld_pencil<AX, NQ, S1, S2>(TEN(CB, c), a, b, v);
                 ld_pencil<AX, NQ, S1, S2>(TEN(6 + CB, c), a, b, r1);
@@ -362,7 +371,7 @@ __global__ void __launch_bounds__(NT)
             constexpr int CB = decltype(cblk)::value, AX = decltype(ax)::value;
             constexpr int E0 = decltype(e0)::value, E1 = decltype(e1)::value, E2 = decltype(e2)::value;
             using O = Others<AX, E0, E1, E2>;
-            pencils<C, O::P0, O::P1, NT>([&](int c, int a, int b) {
+            pencils_part<C, O::P0, O::P1>((CB) * SPAN, SPAN, [&](int c, int a, int b) {
                 T v[NQ], r0[NQ], o[NP];
                 ld_pencil<AX, NQ, S1, S2>(TEN(CB, c), a, b, v);
                 ld_pencil<AX, NQ, S1, S2>(TEN(3 + CB, c), a, b, r0);
@@ -380,7 +389,7 @@ __global__ void __launch_bounds__(NT)
             constexpr int CB = decltype(cblk)::value;
             constexpr int E0 = decltype(e0)::value, E1 = decltype(e1)::value, E2 = decltype(e2)::value;
             using O = Others<CB, E0, E1, E2>;
-            pencils<C, O::P0, O::P1, NT>([&](int c, int a, int b) {
+            pencils_part<C, O::P0, O::P1>((CB) * SPAN, SPAN, [&](int c, int a, int b) {
                 T v[NQ], o[ND];
                 ld_pencil<CB, NQ, S1, S2>(TEN(CB, c), a, b, v);
                 mtv<NQ, ND>(BDT, v, o);
@@ -585,11 +594,11 @@ namespace {
 template <int FAM, int K, typename T, typename IO>
 int launch_action_one(const LaunchArgs &a, const T *tab)
 {
+    // one or two waves per block, C cells so that a block's n^2 pencils fill them
     constexpr int NQ = K + 1;
-    constexpr int PER = 3 * NQ * NQ;
-    constexpr int C = (256 / PER) > 0 ? 256 / PER : 1;
-    constexpr int NT0 = ((C * PER + 63) / 64) * 64;
-    constexpr int NT = NT0 > 256 ? 256 : NT0;
+    constexpr int WB = (FAM == SF_NCE && K == 5) ? 2 : 1;
+    constexpr int NT = 3 * 64 * WB;
+    constexpr int C = (64 * WB) / (NQ * NQ) > 0 ? (64 * WB) / (NQ * NQ) : 1;
     const int64_t groups = (a.ncells + C - 1) / C;
     if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
     const double al = (a.form == SF_MASS) ? 1.0 : a.alpha;
