@@ -242,7 +242,7 @@ int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
  * unit-box cells on an internal stream, (1) the tile size of the batched
  * launch (1, 2, 4, 8 or 16 cell groups per tile; variants 0..4) and (2) for
  * FP64 / FP32 the stand-alone box-cell kernel variants (0: prefetch of the
- * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 3; 2:
+ * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 4; 2:
  * prefetch, >= 2; 3: the general three-tensor kernel that SF_GEOM_AFFINE
  * uses), and records the fastest of each in the context (and, when
  * cache_json_path is non-NULL, merges them into that JSON file, keyed by

@@ -322,12 +322,12 @@ int launch_fast_v(const LaunchArgs &a, const T *tab)
 }
 
 // tile variants (autotuner search space): 0 = prefetch, >= 3 workgroups/CU;
-// 1 = no prefetch, >= 3 workgroups/CU; 2 = prefetch, >= 2 workgroups/CU
+// 1 = no prefetch, >= 4 workgroups/CU; 2 = prefetch, >= 2 workgroups/CU
 template <int N, int FORM, bool COLL, typename T, typename IO>
 int launch_fast(const LaunchArgs &a, const T *tab)
 {
     switch (a.variant) {
-    case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 3>(a, tab);
+    case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 4>(a, tab);
     case 2: return launch_fast_v<N, FORM, COLL, T, IO, true, 2>(a, tab);
     default: return launch_fast_v<N, FORM, COLL, T, IO, true, 3>(a, tab);
     }
