@@ -244,7 +244,8 @@ int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
  * FP64 / FP32 the stand-alone box-cell kernel variants (0: prefetch of the
  * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 4; 2:
  * prefetch, >= 2; 3: the general three-tensor kernel that SF_GEOM_AFFINE
- * uses), and records the fastest of each in the context (and, when
+ * uses; 4 and 5: 128-thread workgroups with and without prefetch), and
+ * records the fastest of each in the context (and, when
  * cache_json_path is non-NULL, merges them into that JSON file, keyed by
  * architecture, family, degree, form, nq1, precision, io dtype and
  * "batch" / "standalone").  Later calls with the same key use the winners.

@@ -38,7 +38,7 @@ template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, in
 __global__ void __launch_bounds__(NT, MINB)
     action_q_fast_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                          const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab,
-                         int *__restrict__ err)
+                         int *__restrict__ err, int *__restrict__ sched)
 {
     static_assert(N == NQ, "the fast kernel assumes n Gauss points per axis");
     static_assert(C * N * N <= NT, "one pencil per thread and stage");
@@ -88,14 +88,32 @@ __global__ void __launch_bounds__(NT, MINB)
         ld_coeff(kappa, pen && gc < ncells, gc * N3 + pr, N2, kreg);
     };
 
-    int64_t g = blockIdx.x;
+    // Group schedule: groups are dealt round-robin (round r gives workgroup b group
+    // b + r gridDim.x).  For the large cells (n >= 7) only three quarters are dealt; the
+    // rest are claimed one at a time, workgroup b from counter b % P of the P = min(8,
+    // gridDim.x) counters in sched (one 128-byte line each), counter x handing out
+    // groups base + x + P k, so that workgroups that run faster take more of them and
+    // all finish within about one group of each other.  Group numbers are fixed two
+    // iterations ahead (thread 0, through LDS) so that the prefetch knows the next one.
+    // A workgroup stops at its first group >= ngroups: dealt groups below the claimed
+    // range are all valid, and a counter's claims only grow, so no claimed group is
+    // left behind.  With fewer than two full rounds the schedule is purely round-robin.
+    constexpr bool DYN = N >= 7;
+    __shared__ int64_t s_claim;
+    const int64_t rounds = DYN ? (ngroups * 3 / 4) / gridDim.x : 0;
+    const int parts = gridDim.x < 8 ? int(gridDim.x) : 8, part = int(blockIdx.x) % parts;
+    int64_t g = blockIdx.x, gn = int64_t(blockIdx.x) + gridDim.x, it = 0;
     if (PREF && g < ngroups) {
         load_v(g);
         load_u(g);
         if constexpr (FORM == SF_LAPLACE) load_k(g);
     }
-    for (; g < ngroups; g += gridDim.x) {
-        const int64_t gn = g + gridDim.x;
+    while (g < ngroups) {
+        int64_t claim = 0; // the group after gn
+        if (tid == 0)
+            claim = (rounds < 2 || it + 2 < rounds)
+                        ? blockIdx.x + (it + 2) * gridDim.x
+                        : rounds * gridDim.x + part + int64_t(parts) * atomicAdd(sched + kSchedLine * part, 1);
         const bool more = PREF && gn < ngroups;
         const int64_t cell0 = g * C;
         if (!PREF) {
@@ -154,7 +172,6 @@ __global__ void __launch_bounds__(NT, MINB)
                 for (int i = 0; i < N; ++i) y[base + i * N2] = IO(s23 * W[i] * k[i] * ureg[i]);
             }
             prefetch_next();
-            continue;
         } else {
             // ---- stage 1 (x): u -> B_x u; for the Laplace form kappa is staged in L1
             // (read back along z, then overwritten by the z stage's output)
@@ -288,6 +305,16 @@ __global__ void __launch_bounds__(NT, MINB)
                 for (int i = 0; i < N; ++i) yo[i * N2] = IO(out[i]);
             }
         }
+        if (tid == 0) s_claim = claim;
+        __syncthreads();
+        g = gn;
+        gn = s_claim;
+        ++it;
+    }
+    // the last workgroup to leave resets the counters for the next launch on this slot
+    if (tid == 0 && atomicAdd(sched + kSchedLine * 8, 1) == int(gridDim.x) - 1) {
+        for (int x = 0; x < 8; ++x) atomicExch(sched + kSchedLine * x, 0);
+        atomicExch(sched + kSchedLine * 8, 0);
     }
 }
 
@@ -306,29 +333,33 @@ template <typename K> int grid_for(K kernel, int nt, int64_t groups, int *cache)
     return int(std::min<int64_t>(groups, *cache));
 }
 
-template <int N, int FORM, bool COLL, typename T, typename IO, bool PREF, int MINB>
+template <int N, int FORM, bool COLL, typename T, typename IO, bool PREF, int MINB, int NT = 256>
 int launch_fast_v(const LaunchArgs &a, const T *tab)
 {
-    constexpr int NT = 256;
     constexpr int C = (NT / (N * N)) > 0 ? NT / (N * N) : 1;
     static int cache = 0;
     const int64_t groups = (a.ncells + C - 1) / C;
     auto kern = action_q_fast_kernel<N, N, FORM, COLL, T, IO, C, NT, PREF, MINB>;
     const int grid = grid_for(kern, NT, groups, &cache);
     if (grid < 0) return SF_ERR_HIP;
+    if (!a.sched) return SF_ERR_ARG;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, a.stream, a.ncells, a.vert, static_cast<const IO *>(a.kappa),
-                       static_cast<const IO *>(a.u), static_cast<IO *>(a.y), tab, a.err);
+                       static_cast<const IO *>(a.u), static_cast<IO *>(a.y), tab, a.err, a.sched);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
-// tile variants (autotuner search space): 0 = prefetch, >= 3 workgroups/CU;
-// 1 = no prefetch, >= 4 workgroups/CU; 2 = prefetch, >= 2 workgroups/CU
+// tile variants (autotuner search space; 3 is the general kernel, launched elsewhere):
+// 256-thread workgroups: 0 = prefetch, >= 3 workgroups/CU; 1 = no prefetch, >= 4;
+// 2 = prefetch, >= 2.  128-thread workgroups (fewer cells per group, more groups in
+// flight): 4 = prefetch, >= 6 workgroups/CU; 5 = no prefetch, >= 8.
 template <int N, int FORM, bool COLL, typename T, typename IO>
 int launch_fast(const LaunchArgs &a, const T *tab)
 {
     switch (a.variant) {
     case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 4>(a, tab);
     case 2: return launch_fast_v<N, FORM, COLL, T, IO, true, 2>(a, tab);
+    case 4: return launch_fast_v<N, FORM, COLL, T, IO, true, 3, 128>(a, tab);
+    case 5: return launch_fast_v<N, FORM, COLL, T, IO, false, 4, 128>(a, tab);
     default: return launch_fast_v<N, FORM, COLL, T, IO, true, 3>(a, tab);
     }
 }

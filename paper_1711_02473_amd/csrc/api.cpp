@@ -302,6 +302,18 @@ int sf_context_create(int hip_device, sf_context **out)
         delete ctx;
         return SF_ERR_HIP;
     }
+    if (hipMalloc(&ctx->d_sched, sizeof(int) * kSchedSlotInts * kSchedSlots) != hipSuccess) {
+        (void)hipFree(ctx->d_err);
+        delete ctx;
+        return SF_ERR_NOMEM;
+    }
+    if (hipMemset(ctx->d_sched, 0, sizeof(int) * kSchedSlotInts * kSchedSlots) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(ctx->d_err);
+        (void)hipFree(ctx->d_sched);
+        delete ctx;
+        return SF_ERR_HIP;
+    }
     *out = ctx;
     return SF_OK;
 }
@@ -317,6 +329,7 @@ int sf_context_destroy(sf_context *ctx)
         if (kv.second.mixed) (void)hipFree(kv.second.mixed);
     }
     (void)hipFree(ctx->d_err);
+    (void)hipFree(ctx->d_sched);
     delete ctx;
     return SF_OK;
 }
@@ -359,6 +372,7 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
         if (ctx->geometry == SF_GEOM_BOX) {
             // variants 0..2: box-cell kernels; 3: the general three-tensor kernel
             a.variant = tuned_variant_of(ctx, op, "standalone", 0);
+            a.sched = ctx->d_sched + kSchedSlotInts * (ctx->sched_next++ % kSchedSlots);
             return a.variant == 3 ? launch_action_q(a) : launch_action_q_fast(a);
         }
         return launch_action_q(a);

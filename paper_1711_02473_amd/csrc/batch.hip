@@ -456,7 +456,7 @@ int sf_load_tuning(sf_context *ctx, const char *path)
 {
     if (!ctx || !path) return SF_ERR_ARG;
     for (auto &kv : read_json(path))
-        if (kv.second >= 0 && kv.second < 5) ctx->tuned[kv.first] = kv.second;
+        if (kv.second >= 0 && kv.second < 6) ctx->tuned[kv.first] = kv.second;
     return SF_OK;
 }
 
@@ -522,7 +522,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
         LaunchArgs a;
         ok = ensure_tables(ctx, op, a) == SF_OK;
         float best_sa_ms = 1e30f;
-        for (int v = 0; ok && v < 4; ++v) {
+        for (int v = 0; ok && v < 6; ++v) {
             a.ncells = nc;
             a.vert = vert;
             a.kappa = kap;
@@ -530,6 +530,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
             a.y = y;
             a.stream = s;
             a.variant = v;
+            a.sched = ctx->d_sched + kSchedSlotInts * (ctx->sched_next++ % kSchedSlots);
             auto run = [&] { return v == 3 ? launch_action_q(a) : launch_action_q_fast(a); };
             ok = run() == SF_OK; // warm-up
             float tot = 0.0f;

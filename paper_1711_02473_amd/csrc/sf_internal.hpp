@@ -79,7 +79,17 @@ struct LaunchArgs {
     int *err;
     hipStream_t stream;
     int variant;
+    // claim counters of a dynamically scheduled persistent launch: 8 claim counters
+    // and one exit counter, each on its own 128-byte line (kSchedLine ints apart),
+    // zero before the launch and reset to zero by the launch's last workgroup
+    int *sched = nullptr;
 };
+
+// ring of counter slots per context: consecutive launches take consecutive slots,
+// so up to kSchedSlots launches from one context may run concurrently
+constexpr int kSchedLine = 32;
+constexpr int kSchedSlotInts = 9 * kSchedLine;
+constexpr int kSchedSlots = 256;
 
 // kernel launchers: return SF_OK, SF_ERR_UNSUPPORTED or SF_ERR_HIP
 int launch_action_q(const LaunchArgs &a);
@@ -98,6 +108,8 @@ int tuned_variant_of(sf_context *ctx, const sf_op *op, const char *what, int dfl
 
 struct sf_context {
     int device = 0;
+    int *d_sched = nullptr; // kSchedSlots slots of kSchedSlotInts counters
+    unsigned sched_next = 0;
     int geometry = SF_GEOM_AFFINE;
     int *d_err = nullptr;
     std::map<std::tuple<int, int, int>, sf::TableSet> tables;

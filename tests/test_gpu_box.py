@@ -22,7 +22,7 @@ from tests.gpu_util import dev, empty, host, max_cell_rel, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-VARIANTS = (0, 1, 2, 3)
+VARIANTS = (0, 1, 2, 3, 4, 5)
 
 
 @pytest.fixture(scope="module")
@@ -167,3 +167,31 @@ def test_box_full_size_sampled(ctx, tmp_path, p):
         yh = host(y[ti])
         assert rel_l2(yh, ref) <= TOL64, (v, rel_l2(yh, ref), max_cell_rel(yh, ref))
         assert bool(torch.isfinite(y).all())
+
+
+def test_box_launches_on_two_streams(ctx, tmp_path):
+    """Persistent box-cell launches claim cell groups from per-launch counters; several
+    launches in flight on different streams, and many in a row on one stream, must each
+    cover every cell exactly once."""
+    import torch
+    p = 5
+    op = sf.make_op("Q", p, "LAPLACE")
+    force_variant(ctx, op, 0, tmp_path)
+    nd = (p + 1) ** 3
+    cases = []
+    for k in range(2):
+        V = synth.box_mesh(4, 5, 6 + k, 16 + k)
+        cases.append((V, synth.kappa(len(V), nd, 16 + k), synth.dof_vector(len(V), nd, 16 + k)))
+    refs = [oracle.action("Q", p, "LAPLACE", V, u, kappa=kap) for V, kap, u in cases]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    dev_in = [(dev(V), dev(kap), dev(u)) for V, kap, u in cases]
+    outs = [empty((len(V), nd), np.float64) for V, _, _ in cases]
+    torch.cuda.synchronize()
+    for rep in range(6):
+        for k in range(2):
+            dV, dk, du = dev_in[k]
+            sf.assemble_action(ctx, op, len(cases[k][0]), dV, dk, du, outs[k], streams[k])
+    torch.cuda.synchronize()
+    assert sf.sf_check_errors(ctx) == 0
+    for k in range(2):
+        assert rel_l2(host(outs[k]), refs[k]) <= TOL64
