@@ -141,9 +141,11 @@ def main():
                          "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "fp64_tflops": round(tfl, 2)}
     dom = max(degrees, key=lambda p: ms[p])
     achieved = action_bytes_per_cell(dom) * ncells / (ms[dom] / 1e3) / 1e9
+    variant = int(tuned.get("gfx950|fam0|p%d|form1|nq%d|prec0|io0|standalone" % (dom, dom + 1), 0))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": "action_q_fast_kernel Q_%d Laplace FP64" % dom,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": recorded_traffic(dom, variant),
+                "kernel": "%s Q_%d Laplace FP64 (variant %d)"
+                          % ("action_q_kernel" if variant == 3 else "action_q_fast_kernel", dom, variant),
                 "bytes_per_launch": action_bytes_per_cell(dom) * ncells}
 
     mixed = None
@@ -189,6 +191,37 @@ def main():
         out["calib_copy_bytes"] = 1 << 30
     print(json.dumps(out))
     ctx.close()
+
+
+def source_digest():
+    """SHA-256 over the library's kernel and interface sources (sorted by path):
+    identifies the kernels a recorded profile was taken from."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1711_02473_amd", "csrc", "*.*"))) + \
+        [os.path.join(ROOT, "include", "sf.h")]
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(p, variant):
+    """HBM bytes per launch of the degree-p action kernel from the committed
+    rocprofv3 counter record (FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the counter reads for a copy of known size), or None when there is no
+    record for this kernel variant and these sources."""
+    path = os.path.join(ROOT, "profiles", "action_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != source_digest() or rec.get("p") != p or rec.get("variant") != variant:
+        return None
+    return rec.get("traffic_bytes")
 
 
 def timed(fn, reps, stream):

@@ -511,7 +511,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
         }
         (void)hipStreamSynchronize(s);
         batch_free(b);
-        if (ok && tot < best_ms) {
+        if (ok && tot < 0.98f * best_ms) { // a later variant must be 2% faster: stable choices
             best_ms = tot;
             best = v;
         }
@@ -541,7 +541,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
                 ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
                 tot += ms;
             }
-            if (ok && tot < best_sa_ms) {
+            if (ok && tot < 0.98f * best_sa_ms) {
                 best_sa_ms = tot;
                 best_sa = v;
             }
