@@ -185,16 +185,10 @@ __global__ void __launch_bounds__(NT)
         fwd_block(I1{}, I1{}, INQ{}, INP{}, INQ{}, BP, DP, 4);
         fwd_block(I2{}, I2{}, INQ{}, INQ{}, INP{}, BP, DP, 5);
         __syncthreads();
-        // pointwise: v = alpha w kappa M1 V, s = beta w kappa div / |J|
+        // pointwise: v = alpha w kappa M1 V, s = beta w kappa div / |J|, one point at a time
+        // (the six values of a point are read, combined and written back in registers)
         pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
             const int64_t gc = cell0 + c;
-            T v0[NQ], v1[NQ], v2[NQ], d0[NQ], d1[NQ], d2[NQ];
-            ld_pencil<0, NQ, S1, S2>(TEN(0, c), q1, q2, v0);
-            ld_pencil<0, NQ, S1, S2>(TEN(1, c), q1, q2, v1);
-            ld_pencil<0, NQ, S1, S2>(TEN(2, c), q1, q2, v2);
-            ld_pencil<0, NQ, S1, S2>(TEN(3, c), q1, q2, d0);
-            ld_pencil<0, NQ, S1, S2>(TEN(4, c), q1, q2, d1);
-            ld_pencil<0, NQ, S1, S2>(TEN(5, c), q1, q2, d2);
             cptr<T> W = fresh(tW);
             const T w12 = W[q1] * W[q2];
             T m[6];
@@ -203,20 +197,19 @@ __global__ void __launch_bounds__(NT)
             const T sb = T(beta * sG[c][12]);
             T kq[NQ];
             ld_coeff(kappa, gc < ncells, gc * NQ3 + q1 * NQ + q2, NQ * NQ, kq);
+            T *t0 = TEN(0, c), *t1 = TEN(1, c), *t2 = TEN(2, c), *t3 = TEN(3, c), *t4 = TEN(4, c), *t5 = TEN(5, c);
 #pragma unroll
             for (int q0 = 0; q0 < NQ; ++q0) {
+                const int o = q0 * S1 + q1 * S2 + q2;
                 const T om = W[q0] * w12 * kq[q0];
                 T x, yv, z;
-                symmv(m, v0[q0], v1[q0], v2[q0], x, yv, z);
-                v0[q0] = om * x;
-                v1[q0] = om * yv;
-                v2[q0] = om * z;
-                d0[q0] = om * sb * (d0[q0] + d1[q0] + d2[q0]);
+                symmv(m, t0[o], t1[o], t2[o], x, yv, z);
+                const T dv = t3[o] + t4[o] + t5[o];
+                t0[o] = om * x;
+                t1[o] = om * yv;
+                t2[o] = om * z;
+                t3[o] = om * sb * dv;
             }
-            st_pencil<0, NQ, S1, S2>(TEN(0, c), q1, q2, v0);
-            st_pencil<0, NQ, S1, S2>(TEN(1, c), q1, q2, v1);
-            st_pencil<0, NQ, S1, S2>(TEN(2, c), q1, q2, v2);
-            st_pencil<0, NQ, S1, S2>(TEN(3, c), q1, q2, d0);
         });
         __syncthreads();
         // backward B1: axis c, T = BP^T v + DP^T s  (NQ -> NP), in place
@@ -290,20 +283,10 @@ __global__ void __launch_bounds__(NT)
             fwd_t(5, I1{}, INQ{}, INP{}, INQ{});
         }
         __syncthreads();
-        // pointwise.  Derivatives present: block 0: d1 V0 (t3), d2 V0 (t6); block 1: d0 V1 (t4),
-        // d2 V1 (t7); block 2: d0 V2 (t5), d1 V2 (t8).
+        // pointwise, one point at a time.  Derivatives present: block 0: d1 V0 (t3), d2 V0 (t6);
+        // block 1: d0 V1 (t4), d2 V1 (t7); block 2: d0 V2 (t5), d1 V2 (t8).
         pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
             const int64_t gc = cell0 + c;
-            T v0[NQ], v1[NQ], v2[NQ], d10[NQ], d20[NQ], d01[NQ], d21[NQ], d02[NQ], d12[NQ];
-            ld_pencil<0, NQ, S1, S2>(TEN(0, c), q1, q2, v0);
-            ld_pencil<0, NQ, S1, S2>(TEN(1, c), q1, q2, v1);
-            ld_pencil<0, NQ, S1, S2>(TEN(2, c), q1, q2, v2);
-            ld_pencil<0, NQ, S1, S2>(TEN(3, c), q1, q2, d10);
-            ld_pencil<0, NQ, S1, S2>(TEN(6, c), q1, q2, d20);
-            ld_pencil<0, NQ, S1, S2>(TEN(4, c), q1, q2, d01);
-            ld_pencil<0, NQ, S1, S2>(TEN(7, c), q1, q2, d21);
-            ld_pencil<0, NQ, S1, S2>(TEN(5, c), q1, q2, d02);
-            ld_pencil<0, NQ, S1, S2>(TEN(8, c), q1, q2, d12);
             cptr<T> W = fresh(tW);
             const T w12 = W[q1] * W[q2];
             T m0[6], m1[6];
@@ -316,35 +299,30 @@ __global__ void __launch_bounds__(NT)
             ld_coeff(kappa, gc < ncells, gc * NQ3 + q1 * NQ + q2, NQ * NQ, kq);
 #pragma unroll
             for (int q0 = 0; q0 < NQ; ++q0) {
+                const int o = q0 * S1 + q1 * S2 + q2;
                 const T om = W[q0] * w12 * kq[q0];
+                const T v0 = TEN(0, c)[o], v1 = TEN(1, c)[o], v2 = TEN(2, c)[o];
+                const T d10 = TEN(3, c)[o], d20 = TEN(6, c)[o], d01 = TEN(4, c)[o];
+                const T d21 = TEN(7, c)[o], d02 = TEN(5, c)[o], d12 = TEN(8, c)[o];
                 // curl^ V = (d1 V2 - d2 V1, d2 V0 - d0 V2, d0 V1 - d1 V0)
-                const T cr0 = d12[q0] - d21[q0], cr1 = d20[q0] - d02[q0], cr2 = d01[q0] - d10[q0];
+                const T cr0 = d12 - d21, cr1 = d20 - d02, cr2 = d01 - d10;
                 T x, yv, z, c0, c1, c2;
-                symmv(m0, v0[q0], v1[q0], v2[q0], x, yv, z);
+                symmv(m0, v0, v1, v2, x, yv, z);
                 symmv(m1, cr0, cr1, cr2, c0, c1, c2);
-                v0[q0] = om * x;
-                v1[q0] = om * yv;
-                v2[q0] = om * z;
                 c0 *= om;
                 c1 *= om;
                 c2 *= om;
+                TEN(0, c)[o] = om * x;
+                TEN(1, c)[o] = om * yv;
+                TEN(2, c)[o] = om * z;
                 // test function phi e_c: curl^ contribution sum_b r_bc d_b phi, r_bc = sum_a eps_abc c_a
-                d10[q0] = -c2; // block 0, d1: r_10 = -c2
-                d20[q0] = c1;  // block 0, d2: r_20 =  c1
-                d01[q0] = c2;  // block 1, d0: r_01 =  c2
-                d21[q0] = -c0; // block 1, d2: r_21 = -c0
-                d02[q0] = -c1; // block 2, d0: r_02 = -c1
-                d12[q0] = c0;  // block 2, d1: r_12 =  c0
+                TEN(3, c)[o] = -c2; // block 0, d1: r_10 = -c2
+                TEN(6, c)[o] = c1;  // block 0, d2: r_20 =  c1
+                TEN(4, c)[o] = c2;  // block 1, d0: r_01 =  c2
+                TEN(7, c)[o] = -c0; // block 1, d2: r_21 = -c0
+                TEN(5, c)[o] = -c1; // block 2, d0: r_02 = -c1
+                TEN(8, c)[o] = c0;  // block 2, d1: r_12 =  c0
             }
-            st_pencil<0, NQ, S1, S2>(TEN(0, c), q1, q2, v0);
-            st_pencil<0, NQ, S1, S2>(TEN(1, c), q1, q2, v1);
-            st_pencil<0, NQ, S1, S2>(TEN(2, c), q1, q2, v2);
-            st_pencil<0, NQ, S1, S2>(TEN(3, c), q1, q2, d10);
-            st_pencil<0, NQ, S1, S2>(TEN(6, c), q1, q2, d20);
-            st_pencil<0, NQ, S1, S2>(TEN(4, c), q1, q2, d01);
-            st_pencil<0, NQ, S1, S2>(TEN(7, c), q1, q2, d21);
-            st_pencil<0, NQ, S1, S2>(TEN(5, c), q1, q2, d02);
-            st_pencil<0, NQ, S1, S2>(TEN(8, c), q1, q2, d12);
         });
         __syncthreads();
         // backward B1: second P axis o1: V <- BP^T V + DP^T r_o1 ; r_o0 <- BP^T r_o0   (NQ -> NP)
@@ -596,7 +574,7 @@ int launch_action_one(const LaunchArgs &a, const T *tab)
 {
     // one or two waves per block, C cells so that a block's n^2 pencils fill them
     constexpr int NQ = K + 1;
-    constexpr int WB = (FAM == SF_NCE && K == 5) ? 2 : 1;
+    constexpr int WB = 1;
     constexpr int NT = 3 * 64 * WB;
     constexpr int C = (64 * WB) / (NQ * NQ) > 0 ? (64 * WB) / (NQ * NQ) : 1;
     const int64_t groups = (a.ncells + C - 1) / C;
