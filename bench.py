@@ -308,13 +308,13 @@ def matrix_leg(sf, ctx, V, degrees, stream, budget_bytes=4 << 30):
     the HBM writes of the matrices: bytes = 8 n^6 + 8 n^3 + 192 per cell."""
     import torch
 
+    from paper_1711_02473_amd import synth
+
     out = {}
-    g = torch.Generator(device="cuda")
-    g.manual_seed(synth_seed() + 50)
     for p in degrees:
         n3 = (p + 1) ** 3
-        nc = int(min(V.shape[0], budget_bytes // (8 * n3 * n3)))
-        kap = torch.rand((nc, n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+        nc = matrix_leg_cells(p, V.shape[0], budget_bytes)
+        kap = synth.device_kappa(nc, n3, 2, p)
         A = torch.empty((nc, n3, n3), device="cuda", dtype=torch.float64)
         op = sf.make_op("Q", p, "LAPLACE")
         sf.assemble_element_matrix(ctx, op, nc, V, kap, A, stream)
@@ -328,9 +328,10 @@ def matrix_leg(sf, ctx, V, degrees, stream, budget_bytes=4 << 30):
     return out
 
 
-def synth_seed():
-    from paper_1711_02473_amd import synth
-    return synth.SEED * 100
+def matrix_leg_cells(p, ncells, budget_bytes=4 << 30):
+    """Cells of the element-matrix leg: the first ones of the mesh, as many as fit."""
+    n3 = (p + 1) ** 3
+    return int(min(ncells, budget_bytes // (8 * n3 * n3)))
 
 
 def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
@@ -352,17 +353,10 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
     del verts
     degs = sorted(set(p for n, p in wl))
     # per degree: one slab of kappa, u, y holding that degree's meshes back to back
-    slab_off, cnt = {}, {p: 0 for p in degs}
-    for m, (n, p) in enumerate(wl):
-        slab_off[m] = cnt[p]
-        cnt[p] += n ** 3
-    g = torch.Generator(device="cuda")
-    g.manual_seed(synth.SEED * 100 + 55)
+    slabs, slab_off = synth.batched_device_inputs(wl)
     kap, u, y, yb = {}, {}, {}, {}
     for p in degs:
-        n3 = (p + 1) ** 3
-        kap[p] = torch.rand((cnt[p], n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
-        u[p] = torch.randn((cnt[p], n3), generator=g, device="cuda", dtype=torch.float64)
+        kap[p], u[p] = slabs[p]
         y[p] = torch.empty_like(u[p])
         yb[p] = torch.empty_like(u[p])
     arena = {p: torch.empty(arena_bytes // 8, device="cuda", dtype=torch.float64) for p in degs}

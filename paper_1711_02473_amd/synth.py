@@ -124,3 +124,33 @@ def device_action_inputs(ncells, n3, config_id, degree, nsets=1):
         u = torch.randn((ncells, n3), generator=g, device="cuda", dtype=torch.float64)
         out.append((kap, u))
     return out
+
+
+def device_kappa(ncells, nq, config_id, degree):
+    """kappa U[0.5, 2], [ncells][nq] FP64 on "cuda", from torch's generator seeded with
+    (config_id, degree) (stream 1 of the recipe)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SEED * 1000 + int(config_id) * 100 + 10 + int(degree))
+    return torch.rand((ncells, nq), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+
+
+def batched_device_inputs(workload, config_id=5):
+    """Inputs of the batched workload on "cuda": per degree p, one slab of kappa and one of
+    u holding that degree's meshes back to back (mesh order), drawn from torch's generator
+    seeded with (config_id, p).  Returns ({p: (kappa, u)}, offset) where offset[m] is mesh
+    m's first row in its degree's slab."""
+    import torch
+    count, offset = {}, []
+    for n, p in workload:
+        offset.append(count.get(p, 0))
+        count[p] = count.get(p, 0) + n ** 3
+    out = {}
+    for p in sorted(count):
+        n3 = (p + 1) ** 3
+        g = torch.Generator(device="cuda")
+        g.manual_seed(SEED * 1000 + int(config_id) * 100 + 20 + p)
+        kap = torch.rand((count[p], n3), generator=g, device="cuda", dtype=torch.float64) * 1.5 + 0.5
+        u = torch.randn((count[p], n3), generator=g, device="cuda", dtype=torch.float64)
+        out[p] = (kap, u)
+    return out, offset

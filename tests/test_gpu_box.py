@@ -141,11 +141,12 @@ def test_geometry_switch_back_to_affine(lib):
         c.close()
 
 
-@pytest.mark.parametrize("p", [1, 2, 5, 8])
-def test_box_full_size_sampled(ctx, tmp_path, p):
-    """The benchmark configuration: 64^3 box cells, kappa per Gauss point, FP64,
-    every variant; sampled cells (first, last, spread, and a run at the end)
-    checked against the oracle cell by cell."""
+@pytest.mark.parametrize("form,p", [("LAPLACE", 1), ("LAPLACE", 2), ("LAPLACE", 5), ("LAPLACE", 8),
+                                    ("MASS", 1), ("MASS", 5), ("MASS", 8)])
+def test_box_full_size_sampled(ctx, tmp_path, form, p):
+    """The benchmark configurations (Laplace headline and mass leg): 64^3 box cells,
+    kappa per Gauss point, FP64, every variant; sampled cells (first, last, spread,
+    and a run at the end) checked against the oracle cell by cell."""
     import torch
     n1 = 64
     n, nd = n1 ** 3, (p + 1) ** 3
@@ -156,10 +157,10 @@ def test_box_full_size_sampled(ctx, tmp_path, p):
     idx = np.unique(np.concatenate([np.arange(0, n, 4099), np.arange(n - 9, n), [0, 1, 2, 3, n // 2]]))
     ti = torch.from_numpy(idx).cuda()
     kh, uh = host(kap[ti]), host(u[ti])
-    ref = oracle.action("Q", p, "LAPLACE", Vh[idx], uh, kappa=kh)
-    op = sf.make_op("Q", p, "LAPLACE")
+    ref = oracle.action("Q", p, form, Vh[idx], uh, kappa=kh)
+    op = sf.make_op("Q", p, form)
     for v in VARIANTS:
-        print("case full-size p", p, "variant", v, flush=True)
+        print("case full-size", form, "p", p, "variant", v, flush=True)
         force_variant(ctx, op, v, tmp_path)
         y.fill_(np.nan)
         sf.assemble_action(ctx, op, n, V, kap, u, y)
