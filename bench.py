@@ -56,7 +56,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--mixed-degrees", default="4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
-    ap.add_argument("--no-tune", action="store_true", help="skip sf_autotune (library defaults)")
+    ap.add_argument("--tune", choices=("cached", "run", "off"), default="cached",
+                    help="kernel variants: 'cached' loads the autotuner's recorded choices for this GPU "
+                         "(paper_1711_02473_amd/tuning/gfx950.json) and tunes what it lacks; 'run' autotunes "
+                         "every degree now; 'off' keeps the library defaults")
+    ap.add_argument("--no-tune", dest="tune", action="store_const", const="off", help="same as --tune off")
+    ap.add_argument("--save-tuning", default="", help="write the tuning choices used to this JSON file")
     ap.add_argument("--legs", default="mass,vec,matrix,batch",
                     help="side measurements beside the headline: mass (Q_p mass action, 64^3), vec (NCF/NCE "
                          "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
@@ -92,13 +97,24 @@ def main():
     # every cell is an axis-aligned box: the library may use its box-cell kernels
     sf.sf_set_geometry(ctx, "box")
     tuned = {}
-    if not args.no_tune:
+    if args.tune != "off":
+        cache = os.path.join(ROOT, "paper_1711_02473_amd", "tuning", "gfx950.json")
+        if args.tune == "cached" and os.path.exists(cache):
+            sf.sf_load_tuning(ctx, cache)
+            with open(cache) as f:
+                tuned = json.load(f)
         with tempfile.TemporaryDirectory() as td:
             path = os.path.join(td, "tune.json")
             for p in degrees:
-                sf.sf_autotune(ctx, ops[p], ncells, path)
-            with open(path) as f:
-                tuned = json.load(f)
+                key = "gfx950|fam0|p%d|form1|nq%d|prec0|io0|standalone" % (p, p + 1)
+                if args.tune == "run" or key not in tuned:
+                    sf.sf_autotune(ctx, ops[p], ncells, path)
+            if os.path.exists(path):
+                with open(path) as f:
+                    tuned.update(json.load(f))
+        if args.save_tuning:
+            with open(args.save_tuning, "w") as f:
+                json.dump(tuned, f, indent=1, sort_keys=True)
     torch.cuda.synchronize()
 
     def step(timers=None, it=0):
