@@ -22,6 +22,9 @@ MUTANTS = [
     ("int pk_axis = (family == ORC_NCF) ? (a == c) : (a != c);",
      "int pk_axis = (family == ORC_NCF) ? (a != c) : (a == c);", "NCF/NCE spaces swapped"),
     ("J[a][b] += X[v * 3 + a] * dphi[b];", "J[a][b] += X[v * 3 + b] * dphi[a];", "J transposed"),
+    ("*w = s->wq[q0] * s->wq[q1] * s->wq[q2];", "*w = s->wq[q0] * s->wq[q1] * s->wq[q1];", "weight: wrong index"),
+    ("double term = 1.0 / (nodes[i] - nodes[k]);", "double term = 1.0 / (nodes[k] - nodes[i]);",
+     "Lagrange derivative: flipped sign"),
 ]
 PIN_SUITES = [os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_golden.py")]
 
