@@ -62,8 +62,9 @@ def main():
                          "every degree now; 'off' keeps the library defaults")
     ap.add_argument("--no-tune", dest="tune", action="store_const", const="off", help="same as --tune off")
     ap.add_argument("--save-tuning", default="", help="write the tuning choices used to this JSON file")
-    ap.add_argument("--legs", default="mass,vec,matrix,batch",
-                    help="side measurements beside the headline: mass (Q_p mass action, 64^3), vec (NCF/NCE "
+    ap.add_argument("--legs", default="mass,global,vec,matrix,batch",
+                    help="side measurements beside the headline: mass (Q_p mass action, 64^3), global (the "
+                         "assembled C0 Q_p Laplace action on global vectors, 64^3), vec (NCF/NCE "
                          "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
                          "launch); '' = none")
     ap.add_argument("--calib-copy", action="store_true",
@@ -174,6 +175,8 @@ def main():
     side = {}
     if "mass" in legs:
         side["mass_action"] = mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, args.steps, stream)
+    if "global" in legs:
+        side["global_action"] = global_leg(sf, ctx, V, bufs, degrees, glob, args.steps, stream)
     if "vec" in legs:
         side["vec_action"] = vec_leg(sf, ctx, args.steps, stream)
     if "matrix" in legs:
@@ -284,6 +287,34 @@ def mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, reps, stream):
         gbs = action_bytes_per_cell(p) * ncells / (ms / 1e3) / 1e9
         out[str(p)] = {"ms": round(ms, 4), "gdofs_global": round(glob[p] / (ms / 1e3) / 1e9, 3),
                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+    assert sf.sf_check_errors(ctx) == 0
+    return out
+
+
+def global_leg(sf, ctx, V, bufs, degrees, glob, reps, stream, n1=NCELL1):
+    """The assembled C0 Q_p Laplace action on global vectors ((64p+1)^3 DOFs): each cell
+    gathers its local DOFs, applies the box-cell action and adds its result with FP64
+    atomics.  Algorithmic bytes: the global u and y once each (8 B per global DOF each;
+    the clearing of y not counted), kappa (8 n^3 per cell) and the vertices."""
+    import torch
+
+    out = {}
+    ncells = n1 ** 3
+    for p in degrees:
+        op = sf.make_op("Q", p, "LAPLACE")
+        kap = bufs[p][0][0]
+        ng = glob[p]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(171102473 * 1000 + 230 + p)
+        ug = torch.randn((2, ng), generator=g, device="cuda", dtype=torch.float64)
+        y = torch.empty((ng,), device="cuda", dtype=torch.float64)
+        sf.assemble_action_global_q(ctx, op, n1, n1, n1, V, kap, ug[0], y, stream)
+        ms = timed(lambda it: sf.assemble_action_global_q(ctx, op, n1, n1, n1, V, kap, ug[it % 2], y, stream),
+                   reps, stream)
+        bts = 16 * ng + (8 * (p + 1) ** 3 + 192) * ncells
+        out[str(p)] = {"ms": round(ms, 4), "gdofs_global": round(ng / (ms / 1e3) / 1e9, 3),
+                       "hbm_gbs": round(bts / (ms / 1e3) / 1e9, 1), "hbm_frac": round(bts / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        del ug, y
     assert sf.sf_check_errors(ctx) == 0
     return out
 

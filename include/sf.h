@@ -121,6 +121,28 @@ const char *sf_status_string(int status);
 #define SF_GEOM_BOX 1
 int sf_set_geometry(sf_context *ctx, int32_t geometry);
 
+/*
+ * Global operator action of continuous Q_p on an nx x ny x nz grid of
+ * axis-aligned box cells (cell (i,j,k) is number (i*ny + j)*nz + k):
+ *   y_global = sum over cells K of P_K^T A_K P_K u_global
+ * (Sec. 1.1: the global operator is the sum of the cell contributions; P_K
+ * gathers cell K's local DOFs).  Local DOF (i0,i1,i2) of cell (i,j,k) is the
+ * lattice point (i p + i0, j p + i1, k p + i2), numbered
+ * (a (ny p + 1) + b)(nz p + 1) + c — the numbering sf_dof_map_q returns.
+ *   op        family SF_Q, form SF_MASS or SF_LAPLACE, SF_FP64, SF_F64
+ *   vertices  device, [nx*ny*nz][8][3] FP64, boxes (others raise SF_FLAG_NONBOX)
+ *   kappa     device, [nx*ny*nz][nq_cell] FP64, or NULL
+ *   u_global  device, [(nx p+1)(ny p+1)(nz p+1)] FP64
+ *   y_global  device, same length, overwritten (cleared by a kernel, then the
+ *             cell contributions are added with FP64 atomics, so the order of
+ *             the additions, and the last bits of y, vary from run to run)
+ * Errors: SF_ERR_ARG, SF_ERR_UNSUPPORTED (other family / form / precision),
+ * SF_ERR_CAPACITY (more than 2^40 global DOFs), SF_ERR_HIP.
+ */
+int assemble_action_global_q(sf_context *ctx, const sf_op *op, int32_t nx, int32_t ny, int32_t nz,
+                             const double *vertices, const void *kappa, const void *u_global, void *y_global,
+                             void *hip_stream);
+
 /* Host only, no GPU needed.  Per-cell local DOF count and quadrature-point
  * count of `op` (after nq1 = 0 => degree + 1), or an error for an
  * unsupported combination.  Validation rules are exactly those of the

@@ -183,6 +183,20 @@ def dofmap_q(nx, ny, nz, p):
     return m, int(nu)
 
 
+def global_action_q(nx, ny, nz, p, form, vertices, u_global, kappa=None):
+    """Global C0 Q_p operator action on an nx x ny x nz cell grid (Sec. 1.1: the global
+    operator is the sum over cells of P_K^T A_K P_K): gather each cell's local DOFs
+    through the brute-force numbering (dofmap_q), apply the direct-quadrature local
+    action, and add every local result into the global vector."""
+    m, nu = dofmap_q(nx, ny, nz, p)
+    u_global = np.ascontiguousarray(u_global, dtype=np.float64)
+    assert u_global.shape == (nu,)
+    y_loc = action("Q", p, form, vertices, u_global[m], kappa=kappa)
+    y = np.zeros(nu)
+    np.add.at(y, m.ravel(), y_loc.ravel())
+    return y
+
+
 def concat_index(extents, block, multi):
     """Flat number of (block, multi-index) in a concatenation of row-major blocks."""
     ext = np.ascontiguousarray(np.asarray(extents, dtype=np.int32))

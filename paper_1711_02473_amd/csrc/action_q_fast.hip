@@ -34,13 +34,18 @@ template <int N, int NQ, int FORM, bool COLL, typename T, int C> struct ActionFa
 // PREF: prefetch the next group's inputs into registers (more registers,
 // latency overlap) or load them when needed; MINB: workgroups per CU the
 // register allocation must allow.
-template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, int NT, bool PREF, int MINB>
+// GLB: u and y are global C0 vectors of an nx x ny x nz cell grid (cell (i,j,k) is
+// number (i*ny + j)*nz + k): local DOFs are gathered through the lattice numbering and
+// the local results are added into y with FP64 atomics (y cleared beforehand).
+template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, int NT, bool PREF, int MINB,
+          bool GLB = false>
 __global__ void __launch_bounds__(NT, MINB)
     action_q_fast_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                          const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab,
-                         int *__restrict__ err, int *__restrict__ sched)
+                         int *__restrict__ err, int *__restrict__ sched, const int gny = 0, const int gnz = 0)
 {
     static_assert(N == NQ, "the fast kernel assumes n Gauss points per axis");
+    static_assert(!(GLB && COLL), "global vectors are for the continuous family");
     static_assert(C * N * N <= NT, "one pencil per thread and stage");
     using L = Lds3<NQ>;
     constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
@@ -77,11 +82,25 @@ __global__ void __launch_bounds__(NT, MINB)
             vreg[r] = (t < 24 * C && g * C + t / 24 < ncells) ? vert[g * C * 24 + t] : 0.0;
         }
     };
+    // global lattice numbering (GLB): local (i0, i1, i2) of cell (ci, cj, ck) is lattice point
+    // (ci p + i0, cj p + i1, ck p + i2), numbered (a (ny p + 1) + b)(nz p + 1) + c
+    constexpr int P = N - 1;
+    const int64_t lz = int64_t(gnz) * P + 1, lyz = (int64_t(gny) * P + 1) * lz;
+    auto gbase = [&](int64_t gc) {
+        const int64_t ci = gc / (int64_t(gny) * gnz), cj = (gc / gnz) % gny, ck = gc % gnz;
+        return (ci * P) * lyz + (cj * P + pa) * lz + ck * P + pb;
+    };
     auto load_u = [&](int64_t g) {
         const int64_t gc = g * C + pc;
         const bool ok = pen && gc < ncells;
+        if constexpr (GLB) {
+            const int64_t b0 = ok ? gbase(gc) : 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) ureg[i] = ok ? T(to_d(u[gc * N3 + i * N2 + pr])) : T(0);
+            for (int i = 0; i < N; ++i) ureg[i] = ok ? T(to_d(u[b0 + i * lyz])) : T(0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) ureg[i] = ok ? T(to_d(u[gc * N3 + i * N2 + pr])) : T(0);
+        }
     };
     auto load_k = [&](int64_t g) {
         const int64_t gc = g * C + pc;
@@ -300,9 +319,15 @@ __global__ void __launch_bounds__(NT, MINB)
                 } else {
                     apply_eo<N, false, false>(BtT, in, out);
                 }
-                IO *yo = y + (cell0 + pc) * N3 + pr;
+                if constexpr (GLB) {
+                    const int64_t b0 = gbase(cell0 + pc);
 #pragma unroll
-                for (int i = 0; i < N; ++i) yo[i * N2] = IO(out[i]);
+                    for (int i = 0; i < N; ++i) unsafeAtomicAdd(y + b0 + i * lyz, IO(out[i]));
+                } else {
+                    IO *yo = y + (cell0 + pc) * N3 + pr;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) yo[i * N2] = IO(out[i]);
+                }
             }
         }
         if (tid == 0) s_claim = claim;
@@ -344,7 +369,7 @@ int launch_fast_v(const LaunchArgs &a, const T *tab)
     if (grid < 0) return SF_ERR_HIP;
     if (!a.sched) return SF_ERR_ARG;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, a.stream, a.ncells, a.vert, static_cast<const IO *>(a.kappa),
-                       static_cast<const IO *>(a.u), static_cast<IO *>(a.y), tab, a.err, a.sched);
+                       static_cast<const IO *>(a.u), static_cast<IO *>(a.y), tab, a.err, a.sched, 0, 0);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
@@ -385,7 +410,57 @@ int fast_n(const LaunchArgs &a)
     return SF_ERR_UNSUPPORTED;
 }
 
+__global__ void fill_zero_kernel(double *y, int64_t n)
+{
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+        y[t] = 0.0;
+}
+
+template <int N, int FORM>
+int launch_global_n(const LaunchArgs &a, int ny, int nz, int64_t nglobal)
+{
+    constexpr int NT = 256;
+    constexpr int C = NT / (N * N) > 0 ? NT / (N * N) : 1;
+    static int cache = 0;
+    const int64_t groups = (a.ncells + C - 1) / C;
+    auto kern = action_q_fast_kernel<N, N, FORM, false, double, double, C, NT, false, 3, true>;
+    const int grid = grid_for(kern, NT, groups, &cache);
+    if (grid < 0 || !a.sched) return SF_ERR_HIP;
+    // clear with a kernel (also inside captured graphs), then accumulate
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(unsigned(std::min<int64_t>(4096, (nglobal + 255) / 256))), dim3(256), 0,
+                       a.stream, static_cast<double *>(a.y), nglobal);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, a.stream, a.ncells, a.vert, static_cast<const double *>(a.kappa),
+                       static_cast<const double *>(a.u), static_cast<double *>(a.y), a.tab64, a.err, a.sched, ny, nz);
+    return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+template <int N>
+int global_form(const LaunchArgs &a, int ny, int nz, int64_t ng)
+{
+    if (a.form == SF_LAPLACE) return launch_global_n<N, SF_LAPLACE>(a, ny, nz, ng);
+    if (a.form == SF_MASS) return launch_global_n<N, SF_MASS>(a, ny, nz, ng);
+    return SF_ERR_UNSUPPORTED;
+}
+
 } // namespace
+
+int launch_action_q_global(const LaunchArgs &a, int nx, int ny, int nz)
+{
+    if (a.family != SF_Q || a.nq != a.degree + 1 || a.precision != SF_FP64 || a.io != SF_F64) return SF_ERR_UNSUPPORTED;
+    const int p = a.degree;
+    const int64_t ng = (int64_t(nx) * p + 1) * (int64_t(ny) * p + 1) * (int64_t(nz) * p + 1);
+    switch (p + 1) {
+    case 2: return global_form<2>(a, ny, nz, ng);
+    case 3: return global_form<3>(a, ny, nz, ng);
+    case 4: return global_form<4>(a, ny, nz, ng);
+    case 5: return global_form<5>(a, ny, nz, ng);
+    case 6: return global_form<6>(a, ny, nz, ng);
+    case 7: return global_form<7>(a, ny, nz, ng);
+    case 8: return global_form<8>(a, ny, nz, ng);
+    case 9: return global_form<9>(a, ny, nz, ng);
+    default: return SF_ERR_UNSUPPORTED;
+    }
+}
 
 int launch_action_q_fast(const LaunchArgs &a)
 {

@@ -380,6 +380,30 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     return launch_action_vec(a);
 }
 
+int assemble_action_global_q(sf_context *ctx, const sf_op *op, int32_t nx, int32_t ny, int32_t nz,
+                             const double *vertices, const void *kappa, const void *u_global, void *y_global,
+                             void *hip_stream)
+{
+    if (!ctx || !op || nx < 1 || ny < 1 || nz < 1) return SF_ERR_ARG;
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    if (op->family != SF_Q || op->precision != SF_FP64 || op->io_dtype != SF_F64 ||
+        (op->form != SF_LAPLACE && op->form != SF_MASS))
+        return SF_ERR_UNSUPPORTED;
+    const int64_t ncells = int64_t(nx) * ny * nz;
+    const int64_t ng = (int64_t(nx) * op->degree + 1) * (int64_t(ny) * op->degree + 1) * (int64_t(nz) * op->degree + 1);
+    if (ng > (int64_t(1) << 40)) return SF_ERR_CAPACITY;
+    if (!vertices || !u_global || !y_global || y_global == u_global || y_global == kappa) return SF_ERR_ARG;
+    LaunchArgs a;
+    rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
+    if (rc) return rc;
+    a.u = u_global;
+    a.y = y_global;
+    a.sched = ctx->d_sched + kSchedSlotInts * (ctx->sched_next++ % kSchedSlots);
+    return launch_action_q_global(a, nx, ny, nz);
+}
+
 int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
                             const void *kappa, void *A, void *hip_stream)
 {

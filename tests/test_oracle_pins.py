@@ -418,3 +418,67 @@ def test_vector_energy_linear_field_affine(family, k):
             cv = np.array([sum(exact1d.EPS[a, bb, c] * B[c, bb] for bb in range(3) for c in range(3)) for a in range(3)])
             d = cv @ cv * S
         assert abs(u @ ad @ u - d) <= 1e-12 * max(d, 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# global C0 action (gather, local action, scatter-add)
+# ---------------------------------------------------------------------------
+
+def _grid_points(nx, ny, nz, p, V):
+    """Physical coordinates of the global lattice nodes of a box grid (GLL nodes per cell)."""
+    x, _ = oracle.gll_rule(p + 1)
+    m, nu = oracle.dofmap_q(nx, ny, nz, p)
+    pts = np.zeros((nu, 3))
+    n = p + 1
+    for c in range(nx * ny * nz):
+        x0 = V[c, 0]
+        h = V[c, 7] - V[c, 0]
+        for i0 in range(n):
+            for i1 in range(n):
+                for i2 in range(n):
+                    pts[m[c, (i0 * n + i1) * n + i2]] = x0 + h * np.array([x[i0], x[i1], x[i2]])
+    return pts
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_global_laplacian_kills_constants_and_is_symmetric(p):
+    nx, ny, nz = 2, 3, 2
+    V = synth.box_mesh(nx, ny, nz, 21)
+    kap = synth.kappa(len(V), (p + 1) ** 3, 21)
+    _, nu = oracle.dofmap_q(nx, ny, nz, p)
+    y = oracle.global_action_q(nx, ny, nz, p, "LAPLACE", V, np.full(nu, 2.5), kappa=kap)
+    assert np.max(np.abs(y)) < 1e-12
+    g = np.random.default_rng(5)
+    u, v = g.standard_normal(nu), g.standard_normal(nu)
+    Au = oracle.global_action_q(nx, ny, nz, p, "LAPLACE", V, u, kappa=kap)
+    Av = oracle.global_action_q(nx, ny, nz, p, "LAPLACE", V, v, kappa=kap)
+    assert abs(v @ Au - u @ Av) <= 1e-12 * abs(v @ Au)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_global_mass_of_ones_sums_to_volume(p):
+    """Every cell contribution is added exactly once: sum_i (M 1)_i = |Omega|."""
+    nx, ny, nz = 3, 2, 2
+    V = synth.box_mesh(nx, ny, nz, 22)
+    _, nu = oracle.dofmap_q(nx, ny, nz, p)
+    y = oracle.global_action_q(nx, ny, nz, p, "MASS", V, np.ones(nu))
+    vol = float(np.prod(V[:, 7] - V[:, 0], axis=1).sum())
+    assert abs(y.sum() - vol) <= 1e-12 * vol
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_global_laplacian_of_linear_field_vanishes_inside(p):
+    """For u linear, integral grad u . grad phi_i = 0 for every basis function phi_i that
+    vanishes on the boundary: the assembled rows of interior nodes are zero, which a
+    wrong gather or scatter (nodes of neighbouring cells mismatched) would break."""
+    nx, ny, nz = 3, 3, 2
+    V = synth.box_mesh(nx, ny, nz, 23)
+    pts = _grid_points(nx, ny, nz, p, V)
+    u = 0.7 * pts[:, 0] - 1.3 * pts[:, 1] + 0.4 * pts[:, 2] + 2.0
+    y = oracle.global_action_q(nx, ny, nz, p, "LAPLACE", V, u)
+    lo, hi = pts.min(axis=0), pts.max(axis=0)
+    inner = np.all((pts > lo + 1e-9) & (pts < hi - 1e-9), axis=1)
+    assert inner.sum() > 0
+    assert np.max(np.abs(y[inner])) < 1e-11 * np.max(np.abs(y))
+    # and the boundary rows carry the flux (not identically zero)
+    assert np.max(np.abs(y[~inner])) > 1e-3
