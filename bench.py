@@ -62,8 +62,9 @@ def main():
                          "every degree now; 'off' keeps the library defaults")
     ap.add_argument("--no-tune", dest="tune", action="store_const", const="off", help="same as --tune off")
     ap.add_argument("--save-tuning", default="", help="write the tuning choices used to this JSON file")
-    ap.add_argument("--legs", default="mass,global,vec,matrix,batch",
-                    help="side measurements beside the headline: mass (Q_p mass action, 64^3), global (the "
+    ap.add_argument("--legs", default="mass,collocated,global,vec,matrix,batch",
+                    help="side measurements beside the headline: mass (Q_p mass action, 64^3), collocated "
+                         "(Laplace action with the GLL rule, B = I, 64^3), global (the "
                          "assembled C0 Q_p Laplace action on global vectors, 64^3), vec (NCF/NCE "
                          "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
                          "launch); '' = none")
@@ -175,6 +176,9 @@ def main():
     side = {}
     if "mass" in legs:
         side["mass_action"] = mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, args.steps, stream)
+    if "collocated" in legs:
+        side["collocated_gll_laplace"] = mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, args.steps, stream,
+                                                  family="QGLL", form="LAPLACE")
     if "global" in legs:
         side["global_action"] = global_leg(sf, ctx, V, bufs, degrees, glob, args.steps, stream)
     if "vec" in legs:
@@ -271,14 +275,16 @@ def measured_copy_gbs():
     return 2.0 * (1 << 30) / (ms / 1e3) / 1e9
 
 
-def mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, reps, stream):
+def mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, reps, stream, family="Q", form="MASS"):
     """Q_p mass action (kappa per Gauss point) on the same 64^3 box mesh, FP64;
-    HBM-bound at every p: bytes = 24 n^3 + 192 per cell."""
+    HBM-bound at every p: bytes = 24 n^3 + 192 per cell.  With family QGLL and form
+    LAPLACE: the collocated GLL Laplace action (B = I, six derivative contractions),
+    same bytes."""
     import torch
 
     out = {}
     for p in degrees:
-        op = sf.make_op("Q", p, "MASS")
+        op = sf.make_op(family, p, form)
         sets = bufs[p]
         y = torch.empty_like(sets[0][1])
         sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], y, stream)

@@ -20,7 +20,8 @@
  *     whose det J <= 0, raises a device-side flag read by sf_check_errors()
  *     and its output is unspecified.  Element matrices additionally require
  *     axis-aligned boxes (diagonal J) and flag other cells the same way.
- *   - Quadrature: nq1 Gauss-Legendre points per axis (tensor rule, eq. tpps),
+ *   - Quadrature: nq1 Gauss-Legendre points per axis (Gauss-Lobatto-Legendre
+ *     for SF_QGLL) (tensor rule, eq. tpps),
  *     point q = (q0*nq1 + q1)*nq1 + q2.  kappa, when given, is a value per
  *     cell per quadrature point, [ncells][nq1^3]; NULL means kappa = 1.
  *   - Elements (Secs. 2.4-2.7): SF_Q = Q_p on Gauss-Lobatto-Legendre nodes,
@@ -33,7 +34,7 @@
  *     indexed-buffer splitting of Concatenate; eq. rtcf_split_x/y).
  *   - Forms (row i = test function, column j = trial function, y = A u):
  *       SF_MASS     int kappa u v        (Piola-mapped for NCF / NCE)
- *       SF_LAPLACE  int kappa grad u . grad v          (SF_Q, SF_DQ)
+ *       SF_LAPLACE  int kappa grad u . grad v          (SF_Q, SF_DQ, SF_QGLL)
  *       SF_HDIV     alpha * mass + beta * int kappa div u div v     (SF_NCF)
  *       SF_HCURL    alpha * mass + beta * int kappa curl u . curl v (SF_NCE)
  *     Contravariant Piola for H(div): Psi = J Psi^ / det J; covariant for
@@ -71,7 +72,12 @@ extern "C" {
 #define SF_FLAG_NONAFFINE 2 /* vertices are not an affine image      */
 #define SF_FLAG_NONBOX 4    /* element matrix on a non-box cell      */
 
-enum { SF_Q = 0, SF_DQ = 1, SF_NCF = 2, SF_NCE = 3 };
+/* SF_QGLL: the Q_p element of SF_Q integrated with the (p+1)-point
+ * Gauss-Lobatto-Legendre rule instead of Gauss-Legendre, so quadrature points
+ * and nodes coincide (B = I): the collocated, under-integrated spectral-element
+ * variant (Sec. 2.5).  Its mass matrix is diagonal (lumped); the 1-D stiffness
+ * is still integrated exactly.  kappa is given at the GLL points. */
+enum { SF_Q = 0, SF_DQ = 1, SF_NCF = 2, SF_NCE = 3, SF_QGLL = 4 };
 enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3 };
 /* contraction precision: FP64, FP32 (both VALU); BF16 / FP16 single-term MFMA
  * with FP32 accumulation; BF16X3 = operands split into three BF16 terms
@@ -86,7 +92,7 @@ typedef struct sf_context sf_context;
 typedef struct sf_batch sf_batch;
 
 typedef struct {
-    int32_t family;    /* SF_Q, SF_DQ: degree p in 1..8;  SF_NCF, SF_NCE: k in 1..6 */
+    int32_t family;    /* SF_Q, SF_DQ, SF_QGLL: degree p in 1..8;  SF_NCF, SF_NCE: k in 1..6 */
     int32_t degree;
     int32_t form;      /* see above                                                 */
     int32_t nq1;       /* GL points per axis; 0 => degree + 1 (see sf_element_dims) */

@@ -55,6 +55,10 @@
 #define ORC_Q 0
 #define ORC_DQ 1
 #define ORC_NCF 2
+/* ORC_QGLL (4): Q_p on GLL nodes integrated with the GLL rule of p+1 points, so that
+ * nodes and quadrature points coincide (the collocated, under-integrated spectral
+ * element variant of Sec. 2.5); the same element as ORC_Q with another rule. */
+#define ORC_QGLL 4
 #define ORC_NCE 3
 
 #define ORC_MASS 0
@@ -199,11 +203,11 @@ static int make_element(int family, int degree, orc_element *e)
     memset(e, 0, sizeof(*e));
     e->family = family;
     e->degree = degree;
-    if (family == ORC_Q || family == ORC_DQ) {
+    if (family == ORC_Q || family == ORC_DQ || family == ORC_QGLL) {
         if (degree < 1 || degree + 1 > ORC_MAXN) return -1;
         e->nblocks = 1;
         e->vector = 0;
-        for (int a = 0; a < 3; ++a) set_axis(&e->b[0], a, degree + 1, family == ORC_Q);
+        for (int a = 0; a < 3; ++a) set_axis(&e->b[0], a, degree + 1, family != ORC_DQ);
         e->b[0].comp = -1;
         e->b[0].offset = 0;
         e->ndof = (degree + 1) * (degree + 1) * (degree + 1);
@@ -387,7 +391,7 @@ static void push_forward(const orc_element *e, const double *val, const double *
  * pushed-forward data of the test (ft) and trial (fs) functions. */
 static double integrand(int family, int form, double alpha, double beta, const double *ft, const double *fs)
 {
-    if (family == ORC_Q || family == ORC_DQ) {
+    if (family == ORC_Q || family == ORC_DQ || family == ORC_QGLL) {
         if (form == ORC_MASS) return ft[0] * fs[0];
         return ft[1] * fs[1] + ft[2] * fs[2] + ft[3] * fs[3]; /* LAPLACE */
     }
@@ -399,7 +403,7 @@ static double integrand(int family, int form, double alpha, double beta, const d
 
 static int form_valid(int family, int form)
 {
-    if (family == ORC_Q || family == ORC_DQ) return form == ORC_MASS || form == ORC_LAPLACE;
+    if (family == ORC_Q || family == ORC_DQ || family == ORC_QGLL) return form == ORC_MASS || form == ORC_LAPLACE;
     if (family == ORC_NCF) return form == ORC_MASS || form == ORC_HDIV;
     if (family == ORC_NCE) return form == ORC_MASS || form == ORC_HCURL;
     return 0;
@@ -420,7 +424,12 @@ static int setup(int family, int degree, int form, int nq1, orc_setup *s)
     if (nq1 > ORC_MAXN) return -3;
     s->nq1 = nq1;
     s->nq = nq1 * nq1 * nq1;
-    orc_gauss_legendre(nq1, s->xq, s->wq);
+    if (family == ORC_QGLL) {
+        if (nq1 < 2) return -3;
+        orc_gauss_lobatto(nq1, s->xq, s->wq);
+    } else {
+        orc_gauss_legendre(nq1, s->xq, s->wq);
+    }
     int nd = s->e.ndof;
     s->val = (double *)malloc(sizeof(double) * (size_t)s->nq * nd * 3);
     s->grad = (double *)malloc(sizeof(double) * (size_t)s->nq * nd * 9);

@@ -69,7 +69,7 @@ int launch_prec(const LaunchArgs &a)
 template <int N>
 int launch_n(const LaunchArgs &a)
 {
-    const bool coll = a.family == SF_DQ;
+    const bool coll = a.family == SF_DQ || a.family == SF_QGLL; // B = I
     if (a.form == SF_MASS) return coll ? launch_prec<N, SF_MASS, true>(a) : launch_prec<N, SF_MASS, false>(a);
     if (a.form == SF_LAPLACE) return coll ? launch_prec<N, SF_LAPLACE, true>(a) : launch_prec<N, SF_LAPLACE, false>(a);
     return SF_ERR_UNSUPPORTED;

@@ -404,7 +404,7 @@ int fast_prec(const LaunchArgs &a)
 template <int N>
 int fast_n(const LaunchArgs &a)
 {
-    const bool coll = a.family == SF_DQ;
+    const bool coll = a.family == SF_DQ || a.family == SF_QGLL; // B = I
     if (a.form == SF_MASS) return coll ? fast_prec<N, SF_MASS, true>(a) : fast_prec<N, SF_MASS, false>(a);
     if (a.form == SF_LAPLACE) return coll ? fast_prec<N, SF_LAPLACE, true>(a) : fast_prec<N, SF_LAPLACE, false>(a);
     return SF_ERR_UNSUPPORTED;

@@ -19,11 +19,12 @@ struct Dims {
     int nq1, ndof, nq, n0, n1;
 };
 
-int degree_max(int family) { return (family == SF_Q || family == SF_DQ) ? 8 : 6; }
+bool scalar_family(int family) { return family == SF_Q || family == SF_DQ || family == SF_QGLL; }
+int degree_max(int family) { return scalar_family(family) ? 8 : 6; }
 
 bool form_ok(int family, int form)
 {
-    if (family == SF_Q || family == SF_DQ) return form == SF_MASS || form == SF_LAPLACE;
+    if (scalar_family(family)) return form == SF_MASS || form == SF_LAPLACE;
     if (family == SF_NCF) return form == SF_MASS || form == SF_HDIV;
     if (family == SF_NCE) return form == SF_MASS || form == SF_HCURL;
     return false;
@@ -33,7 +34,7 @@ bool form_ok(int family, int form)
 int check_op(const sf_op *op, Dims *d)
 {
     if (!op) return SF_ERR_ARG;
-    if (op->family < SF_Q || op->family > SF_NCE) return SF_ERR_UNSUPPORTED;
+    if (op->family < SF_Q || op->family > SF_QGLL) return SF_ERR_UNSUPPORTED;
     if (op->degree < 1 || op->degree > degree_max(op->family)) return SF_ERR_UNSUPPORTED;
     if (!form_ok(op->family, op->form)) return SF_ERR_UNSUPPORTED;
     if (op->nq1 < 0) return SF_ERR_ARG;
@@ -46,7 +47,7 @@ int check_op(const sf_op *op, Dims *d)
     Dims r;
     r.nq1 = nq1;
     r.nq = nq1 * nq1 * nq1;
-    if (op->family == SF_Q || op->family == SF_DQ) {
+    if (scalar_family(op->family)) {
         r.n0 = p + 1;
         r.n1 = 0;
         r.ndof = (p + 1) * (p + 1) * (p + 1);
@@ -146,7 +147,8 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
     TabLayout L(d.n0, d.n1, d.nq1);
     std::vector<double> h(L.size(), 0.0);
     std::vector<double> xq(d.nq1), wq(d.nq1), n0(d.n0), w0(d.n0), n1(std::max(d.n1, 1)), w1(std::max(d.n1, 1));
-    rule_1d(0, d.nq1, xq.data(), wq.data());
+    // quadrature: GL, or GLL for the collocated variant (nodes = points, B = I)
+    rule_1d(op->family == SF_QGLL ? 1 : 0, d.nq1, xq.data(), wq.data());
     if (op->family == SF_DQ) rule_1d(0, d.n0, n0.data(), w0.data());
     else rule_1d(1, d.n0, n0.data(), w0.data()); // Q_p and the P_k factor: GLL nodes
     lagrange_table(d.n0, n0.data(), d.nq1, xq.data(), h.data() + L.B0(), h.data() + L.D0());
@@ -188,7 +190,7 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
         (void)hipFree(ts.f32);
         return SF_ERR_HIP;
     }
-    if (op->family == SF_Q || op->family == SF_DQ) {
+    if (scalar_family(op->family)) {
         std::vector<uint16_t> mp = mixed_planes(h, L, d.n0, d.nq1);
         if (hipMalloc(&ts.mixed, sizeof(uint16_t) * mp.size()) != hipSuccess) {
             (void)hipFree(ts.d64);
@@ -368,7 +370,7 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     a.y = y;
     if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
         return launch_action_mixed(a);
-    if (op->family == SF_Q || op->family == SF_DQ) {
+    if (scalar_family(op->family)) {
         if (ctx->geometry == SF_GEOM_BOX) {
             // variants 0..2: box-cell kernels; 3: the general three-tensor kernel
             a.variant = tuned_variant_of(ctx, op, "standalone", 0);
@@ -418,7 +420,7 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
     rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
     if (rc) return rc;
     a.A = A;
-    if (op->family == SF_Q || op->family == SF_DQ) return launch_matrix_q(a);
+    if (scalar_family(op->family)) return launch_matrix_q(a);
     return launch_matrix_vec(a);
 }
 
@@ -472,7 +474,7 @@ int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t
     if (rc) return rc;
     if (!nblocks || !extents || !offsets) return SF_ERR_ARG;
     const int p = op->degree;
-    if (op->family == SF_Q || op->family == SF_DQ) {
+    if (scalar_family(op->family)) {
         *nblocks = 1;
         extents[0] = extents[1] = extents[2] = p + 1;
         offsets[0] = 0;

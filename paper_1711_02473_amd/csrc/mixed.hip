@@ -77,7 +77,7 @@ int launch_mode(const LaunchArgs &a)
 template <int N>
 int launch_n(const LaunchArgs &a)
 {
-    const bool coll = a.family == SF_DQ;
+    const bool coll = a.family == SF_DQ || a.family == SF_QGLL; // B = I
     if (a.form == SF_LAPLACE) return coll ? launch_mode<N, SF_LAPLACE, true>(a) : launch_mode<N, SF_LAPLACE, false>(a);
     if (a.form == SF_MASS) return coll ? launch_mode<N, SF_MASS, true>(a) : launch_mode<N, SF_MASS, false>(a);
     return SF_ERR_UNSUPPORTED;
@@ -87,7 +87,7 @@ int launch_n(const LaunchArgs &a)
 
 int launch_action_mixed(const LaunchArgs &a)
 {
-    if (a.family != SF_Q && a.family != SF_DQ) return SF_ERR_UNSUPPORTED;
+    if (a.family != SF_Q && a.family != SF_DQ && a.family != SF_QGLL) return SF_ERR_UNSUPPORTED;
     if (a.nq != a.degree + 1 || !a.tabmix) return SF_ERR_UNSUPPORTED;
     switch (a.degree + 1) {
     case 2: return launch_n<2>(a);

@@ -55,7 +55,7 @@ def launch(ctx, op, V, kap, u, io=np.float64):
     return host(dy), flags
 
 
-@pytest.mark.parametrize("family", ["Q", "DQ"])
+@pytest.mark.parametrize("family", ["Q", "DQ", "QGLL"])
 @pytest.mark.parametrize("form", ["LAPLACE", "MASS"])
 @pytest.mark.parametrize("p", range(1, 9))
 def test_box_action_fp64_all_variants(ctx, tmp_path, family, form, p):

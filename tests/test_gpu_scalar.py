@@ -53,7 +53,7 @@ def run_matrix(ctx, op, V, kap, io=np.float64):
     return host(dA), flags
 
 
-@pytest.mark.parametrize("family", ["Q", "DQ"])
+@pytest.mark.parametrize("family", ["Q", "DQ", "QGLL"])
 @pytest.mark.parametrize("form", ["LAPLACE", "MASS"])
 @pytest.mark.parametrize("p", range(1, 9))
 def test_action_fp64_boxes(ctx, family, form, p):
@@ -99,7 +99,7 @@ def test_config1_q2_laplace(ctx):
     assert max_cell_rel(A, Ar) <= 10 * TOL64
 
 
-@pytest.mark.parametrize("family", ["Q", "DQ"])
+@pytest.mark.parametrize("family", ["Q", "DQ", "QGLL"])
 @pytest.mark.parametrize("form", ["LAPLACE", "MASS"])
 @pytest.mark.parametrize("p", range(1, 9))
 def test_element_matrix_fp64(ctx, family, form, p):

@@ -482,3 +482,42 @@ def test_global_laplacian_of_linear_field_vanishes_inside(p):
     assert np.max(np.abs(y[inner])) < 1e-11 * np.max(np.abs(y))
     # and the boundary rows carry the flux (not identically zero)
     assert np.max(np.abs(y[~inner])) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# collocated GLL variant (Q_p on GLL nodes with the (p+1)-point GLL rule)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_qgll_box_matrices_are_lumped_kroneckers(p):
+    """Nodes and points coincide, so the mass matrix is the diagonal of the GLL
+    weights (lumped mass), and the rule is exact for the 1-D stiffness (degree
+    2p - 2 <= 2(p+1) - 3): on a box the Laplacian is sum_d K_d (x) W (x) W with the
+    exact 1-D stiffness K and W = diag(w).  The weights here come from exact
+    integration of the Lagrange basis, not from the oracle's rule."""
+    h = (0.6, 1.4, 0.9)
+    V = exact1d.box_vertices(h, x0=(1.0, 0.5, -2.0))[None]
+    nodes = GLL(p + 1)
+    w = np.array([exact1d.integrate01(c) for c in exact1d.lagrange_coeffs(nodes)])
+    W = np.diag(w)
+    K = exact1d.matrix1d(nodes, 1, nodes, 1)
+    vol = h[0] * h[1] * h[2]
+    M = oracle.element_matrix("QGLL", p, "MASS", V)[0]
+    assert np.abs(M - vol * exact1d.kron3(W, W, W)).max() <= 1e-13 * vol
+    A = oracle.element_matrix("QGLL", p, "LAPLACE", V)[0]
+    R = vol * (exact1d.kron3(K, W, W) / h[0] ** 2 + exact1d.kron3(W, K, W) / h[1] ** 2 +
+               exact1d.kron3(W, W, K) / h[2] ** 2)
+    assert np.abs(A - R).max() <= 1e-11 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_qgll_differs_from_exact_quadrature_only_in_the_mass(p):
+    """Same element as Q_p: the Laplacian on a box agrees with the exactly
+    integrated one only where the rule is exact; the GLL mass is diagonal while
+    the exact Q_p mass is not."""
+    V = synth.box_mesh(1, 1, 1, 26)
+    Mq = oracle.element_matrix("Q", p, "MASS", V)[0]
+    Mg = oracle.element_matrix("QGLL", p, "MASS", V)[0]
+    assert np.abs(Mg - np.diag(np.diag(Mg))).max() == 0.0
+    assert np.abs(Mq - np.diag(np.diag(Mq))).max() > 1e-3 * np.abs(Mq).max()
+    assert abs(Mg.sum() - Mq.sum()) <= 1e-13 * Mq.sum()  # both integrate 1 exactly
