@@ -62,9 +62,10 @@ def main():
                          "every degree now; 'off' keeps the library defaults")
     ap.add_argument("--no-tune", dest="tune", action="store_const", const="off", help="same as --tune off")
     ap.add_argument("--save-tuning", default="", help="write the tuning choices used to this JSON file")
-    ap.add_argument("--legs", default="mass,collocated,global,vec,matrix,batch",
+    ap.add_argument("--legs", default="mass,collocated,trilinear,global,vec,matrix,batch",
                     help="side measurements beside the headline: mass (Q_p mass action, 64^3), collocated "
-                         "(Laplace action with the GLL rule, B = I, 64^3), global (the "
+                         "(Laplace action with the GLL rule, B = I, 64^3), trilinear (Laplace action on general "
+                         "trilinear cells, per-point geometry, 64^3 cells), global (the "
                          "assembled C0 Q_p Laplace action on global vectors, 64^3), vec (NCF/NCE "
                          "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
                          "launch); '' = none")
@@ -179,6 +180,8 @@ def main():
     if "collocated" in legs:
         side["collocated_gll_laplace"] = mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, args.steps, stream,
                                                   family="QGLL", form="LAPLACE")
+    if "trilinear" in legs:
+        side["trilinear_laplace"] = trilinear_leg(sf, V.shape[0], degrees, bufs, args.steps, stream)
     if "global" in legs:
         side["global_action"] = global_leg(sf, ctx, V, bufs, degrees, glob, args.steps, stream)
     if "vec" in legs:
@@ -294,6 +297,35 @@ def mass_leg(sf, ctx, V, bufs, ncells, degrees, glob, reps, stream, family="Q", 
         out[str(p)] = {"ms": round(ms, 4), "gdofs_global": round(glob[p] / (ms / 1e3) / 1e9, 3),
                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
     assert sf.sf_check_errors(ctx) == 0
+    return out
+
+
+def trilinear_leg(sf, ncells, degrees, bufs, reps, stream):
+    """Q_p Laplace action on general trilinear hexahedra (every vertex of a unit-ish
+    cube moved by up to 0.15; a separate context with geometry SF_GEOM_TRILINEAR), the
+    geometric factor computed at every Gauss point; same kappa and u as the headline.
+    Bytes as the headline (24 n^3 + 192 per cell)."""
+    import torch
+
+    from paper_1711_02473_amd import synth
+
+    c = sf.Context(0)
+    sf.sf_set_geometry(c, "trilinear")
+    Vt = torch.from_numpy(synth.trilinear_cells(ncells, 7)).cuda()
+    out = {}
+    for p in degrees:
+        op = sf.make_op("Q", p, "LAPLACE")
+        sets = bufs[p]
+        y = torch.empty_like(sets[0][1])
+        sf.assemble_action(c, op, ncells, Vt, sets[0][0], sets[0][1], y, stream)
+        ms = timed(lambda it: sf.assemble_action(c, op, ncells, Vt, sets[it % len(sets)][0], sets[it % len(sets)][1],
+                                                 y, stream), reps, stream)
+        gbs = action_bytes_per_cell(p) * ncells / (ms / 1e3) / 1e9
+        out[str(p)] = {"ms": round(ms, 4), "gdofs_local": round(ncells * (p + 1) ** 3 / (ms / 1e3) / 1e9, 3),
+                       "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+        del y
+    assert sf.sf_check_errors(c) == 0
+    c.close()
     return out
 
 

@@ -125,6 +125,14 @@ const char *sf_status_string(int status);
  * an unknown value. */
 #define SF_GEOM_AFFINE 0
 #define SF_GEOM_BOX 1
+/* SF_GEOM_TRILINEAR: cells may be general trilinear hexahedra (the vector-Q1
+ * coordinate field, Sec. 3.1); the Q_p / dQ_p / SF_QGLL actions then evaluate
+ * J, |J| and |J| G G^T at every quadrature point (the per-point factor
+ * P^{(k,l)}_q of Sec. 3.2, all six entries) in FP64 and need SF_FP64 with
+ * SF_F64 storage (else SF_ERR_UNSUPPORTED); a point with det J <= 0 raises
+ * SF_FLAG_DETJ.  Element matrices, the H(div) / H(curl) kernels and the
+ * lower-precision actions keep their affine / box requirements. */
+#define SF_GEOM_TRILINEAR 2
 int sf_set_geometry(sf_context *ctx, int32_t geometry);
 
 /*

@@ -24,7 +24,7 @@ SF_ERR_HIP = -4
 SF_ERR_GEOMETRY = -5
 SF_ERR_CAPACITY = -6
 SF_FLAG_DETJ, SF_FLAG_NONAFFINE, SF_FLAG_NONBOX = 1, 2, 4
-SF_GEOM_AFFINE, SF_GEOM_BOX = 0, 1
+SF_GEOM_AFFINE, SF_GEOM_BOX, SF_GEOM_TRILINEAR = 0, 1, 2
 
 
 class SfOp(ctypes.Structure):
@@ -144,8 +144,9 @@ class Context:
 
 
 def sf_set_geometry(ctx, geometry):
-    """SF_GEOM_AFFINE (default) or SF_GEOM_BOX (the caller guarantees axis-aligned boxes)."""
-    g = {"affine": SF_GEOM_AFFINE, "box": SF_GEOM_BOX}.get(geometry, geometry)
+    """SF_GEOM_AFFINE (default), SF_GEOM_BOX (the caller guarantees axis-aligned boxes) or
+    SF_GEOM_TRILINEAR (general trilinear hexahedra, geometry per quadrature point)."""
+    g = {"affine": SF_GEOM_AFFINE, "box": SF_GEOM_BOX, "trilinear": SF_GEOM_TRILINEAR}.get(geometry, geometry)
     return _check(_lib().sf_set_geometry(ctx.handle, int(g)), "sf_set_geometry")
 
 

@@ -26,27 +26,27 @@
 namespace sf {
 
 
-template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, int NT>
+template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, int NT, bool TRI>
 __global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, const double *__restrict__ vert,
                                                       const IO *__restrict__ kappa, const IO *__restrict__ u,
                                                       IO *__restrict__ y, const T *__restrict__ tab,
                                                       int *__restrict__ err)
 {
     __shared__ double smem[ActionQSmem<N, NQ, FORM, COLL, T, C>::bytes / 8];
-    action_q_body<N, NQ, FORM, COLL, T, IO, C, NT>(int64_t(blockIdx.x) * C, ncells, vert, kappa, u, y, tab, err,
-                                                   smem);
+    action_q_body<N, NQ, FORM, COLL, T, IO, C, NT, TRI>(int64_t(blockIdx.x) * C, ncells, vert, kappa, u, y, tab,
+                                                        err, smem);
 }
 
 namespace {
 
-template <int N, int NQ, int FORM, bool COLL, typename T, typename IO>
+template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, bool TRI = false>
 int launch_one(const LaunchArgs &a, const T *tab)
 {
     constexpr int NT = 256;
     constexpr int C = (NT / (NQ * NQ)) > 0 ? NT / (NQ * NQ) : 1;
     const int64_t groups = (a.ncells + C - 1) / C;
     if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
-    hipLaunchKernelGGL((action_q_kernel<N, NQ, FORM, COLL, T, IO, C, NT>), dim3(unsigned(groups)), dim3(NT), 0,
+    hipLaunchKernelGGL((action_q_kernel<N, NQ, FORM, COLL, T, IO, C, NT, TRI>), dim3(unsigned(groups)), dim3(NT), 0,
                        a.stream, a.ncells, a.vert, static_cast<const IO *>(a.kappa), static_cast<const IO *>(a.u),
                        static_cast<IO *>(a.y), tab, a.err);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
@@ -55,6 +55,10 @@ int launch_one(const LaunchArgs &a, const T *tab)
 template <int N, int FORM, bool COLL>
 int launch_prec(const LaunchArgs &a)
 {
+    if (a.trilinear) { // per-point geometry: FP64 contractions, FP64 storage
+        if (a.precision != SF_FP64 || a.io != SF_F64) return SF_ERR_UNSUPPORTED;
+        return launch_one<N, N, FORM, COLL, double, double, true>(a, a.tab64);
+    }
     if (a.precision == SF_FP64) {
         if (a.io == SF_F64) return launch_one<N, N, FORM, COLL, double, double>(a, a.tab64);
         return launch_one<N, N, FORM, COLL, double, float>(a, a.tab64);

@@ -159,6 +159,7 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
     std::vector<double> tmpB(size_t(d.nq1) * d.nq1);
     lagrange_table(d.nq1, xq.data(), d.nq1, xq.data(), tmpB.data(), h.data() + L.Dh());
     std::copy(wq.begin(), wq.end(), h.begin() + L.W());
+    std::copy(xq.begin(), xq.end(), h.begin() + L.XQ());
     auto transpose = [&](int src, int dst, int rows, int cols) {
         for (int r = 0; r < rows; ++r)
             for (int c = 0; c < cols; ++c) h[dst + size_t(c) * rows + r] = h[src + size_t(r) * cols + c];
@@ -338,7 +339,8 @@ int sf_context_destroy(sf_context *ctx)
 
 int sf_set_geometry(sf_context *ctx, int32_t geometry)
 {
-    if (!ctx || (geometry != SF_GEOM_AFFINE && geometry != SF_GEOM_BOX)) return SF_ERR_ARG;
+    if (!ctx || (geometry != SF_GEOM_AFFINE && geometry != SF_GEOM_BOX && geometry != SF_GEOM_TRILINEAR))
+        return SF_ERR_ARG;
     ctx->geometry = geometry;
     return SF_OK;
 }
@@ -371,6 +373,10 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
         return launch_action_mixed(a);
     if (scalar_family(op->family)) {
+        if (ctx->geometry == SF_GEOM_TRILINEAR) {
+            a.trilinear = true;
+            return launch_action_q(a);
+        }
         if (ctx->geometry == SF_GEOM_BOX) {
             // variants 0..2: box-cell kernels; 3: the general three-tensor kernel
             a.variant = tuned_variant_of(ctx, op, "standalone", 0);

@@ -254,6 +254,37 @@ template <int C, int P0, int P1, typename F> __device__ __forceinline__ void pen
     }
 }
 
+// Jacobian of the trilinear (vector-Q1) coordinate map at reference point xi:
+// x(xi) = sum_v X_v phi_v(xi), phi_v = prod_d (v_d ? xi_d : 1 - xi_d) for the
+// vertex v = 4 v0 + 2 v1 + v2 (Sec. 3.1, the coordinate field evaluated at a
+// quadrature point); J[a][b] = d x_a / d xi_b.  Returns det J.
+__device__ inline double trilinear_jacobian(const double *__restrict__ X, double x0, double x1, double x2,
+                                            double J[3][3])
+{
+    const double f[3][2] = {{1.0 - x0, x0}, {1.0 - x1, x1}, {1.0 - x2, x2}};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) J[a][b] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int v0 = v >> 2, v1 = (v >> 1) & 1, v2 = v & 1;
+        const double s0 = v0 ? 1.0 : -1.0, s1 = v1 ? 1.0 : -1.0, s2 = v2 ? 1.0 : -1.0;
+        const double d0 = s0 * f[1][v1] * f[2][v2];
+        const double d1 = f[0][v0] * s1 * f[2][v2];
+        const double d2 = f[0][v0] * f[1][v1] * s2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double xa = X[3 * v + a];
+            J[a][0] = fma(xa, d0, J[a][0]);
+            J[a][1] = fma(xa, d1, J[a][1]);
+            J[a][2] = fma(xa, d2, J[a][2]);
+        }
+    }
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
 // Affine cell geometry from the 8 vertices (vector-Q1 coordinate field with
 // the delta-cancelled scalar Q1 table, Sec. 3.1, evaluated for an affine map):
 // J = [x(1,0,0)-x0, x(0,1,0)-x0, x(0,0,1)-x0]; the remaining vertices must be

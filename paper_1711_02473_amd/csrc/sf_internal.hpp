@@ -52,7 +52,8 @@ struct TabLayout {
     __host__ __device__ constexpr int BTEO() const { return BEO() + eo_len(nq); }
     __host__ __device__ constexpr int DhEO() const { return BTEO() + eo_len(nq); }
     __host__ __device__ constexpr int DhTEO() const { return DhEO() + eo_len(nq); }
-    __host__ __device__ constexpr int size() const { return DhTEO() + eo_len(nq); }
+    __host__ __device__ constexpr int XQ() const { return DhTEO() + eo_len(nq); } // quadrature points
+    __host__ __device__ constexpr int size() const { return XQ() + nq; }
 };
 
 // Tables split into three bf16 terms (hi, mid, lo) and single fp16 / bf16
@@ -83,6 +84,8 @@ struct LaunchArgs {
     // and one exit counter, each on its own 128-byte line (kSchedLine ints apart),
     // zero before the launch and reset to zero by the launch's last workgroup
     int *sched = nullptr;
+    // cells are general trilinear hexahedra: geometry per quadrature point
+    bool trilinear = false;
 };
 
 // ring of counter slots per context: consecutive launches take consecutive slots,
