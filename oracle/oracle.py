@@ -54,6 +54,8 @@ def load():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp, dp]
     lib.orc_action.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp, dp, dp]
+    lib.orc_svk.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_int, ctypes.c_long, dp, dp, dp, dp]
     lib.orc_dofmap_q.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
     lib.orc_dofmap_q.restype = ctypes.c_long
     lib.orc_concat_index.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, ip]
@@ -171,6 +173,45 @@ def action(family, degree, form, vertices, u, kappa=None, nq1=0, alpha=1.0, beta
     if rc > 0 and check_geometry:
         raise ValueError("det J <= 0 in cell %d" % (rc - 1))
     return y
+
+
+def _svk(mode, family, degree, vertices, u0, du, lam, mu, nq1, check_geometry):
+    m = _nq1(family, degree, nq1)
+    vertices = np.ascontiguousarray(vertices, dtype=np.float64)
+    ncells = vertices.shape[0]
+    assert vertices.shape[1:] == (8, 3)
+    nd = 3 * ndof(family, degree)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    assert u0.shape == (ncells, nd), (u0.shape, (ncells, nd))
+    dp = None
+    if du is not None:
+        du = np.ascontiguousarray(du, dtype=np.float64)
+        assert du.shape == (ncells, nd)
+        dp = _dp(du)
+    out = np.zeros(ncells if mode == 0 else (ncells, nd))
+    rc = load().orc_svk(FAMILIES[family], degree, m, float(lam), float(mu), mode, ncells, _dp(vertices),
+                        _dp(u0), dp, _dp(out))
+    if rc < 0:
+        raise ValueError("oracle rejected arguments (%d)" % rc)
+    if rc > 0 and check_geometry:
+        raise ValueError("det J <= 0 in cell %d" % (rc - 1))
+    return out
+
+
+def svk_energy(family, degree, vertices, u0, lam, mu, nq1=0, check_geometry=True):
+    """Saint Venant-Kirchhoff strain energy per cell, sum_q w |J| W(E(u0)) (family Q or QGLL;
+    u0 [ncells][3 ndof], component-major: DOF (c, i) at c * ndof + i)."""
+    return _svk(0, family, degree, vertices, u0, None, lam, mu, nq1, check_geometry)
+
+
+def svk_residual(family, degree, vertices, u0, lam, mu, nq1=0, check_geometry=True):
+    """Residual action y[c][(c', i)] = int P(u0) : grad(psi_i e_c') (no body force)."""
+    return _svk(1, family, degree, vertices, u0, None, lam, mu, nq1, check_geometry)
+
+
+def svk_jacobian_action(family, degree, vertices, u0, du, lam, mu, nq1=0, check_geometry=True):
+    """Action of the linearised residual at u0 on du: int dP(u0; du) : grad(psi_i e_c')."""
+    return _svk(2, family, degree, vertices, u0, du, lam, mu, nq1, check_geometry)
 
 
 def dofmap_q(nx, ny, nz, p):

@@ -573,6 +573,143 @@ int orc_action(int family, int degree, int form, int nq1, double alpha, double b
 }
 
 /* ------------------------------------------------------------------------ */
+/* Saint Venant-Kirchhoff hyperelasticity on the vector Q_p element: the    */
+/* hyperelastic model of the paper's evaluation (strain energy, first       */
+/* Piola-Kirchhoff stress, residual form, and the bilinear form obtained by */
+/* linearising the residual, eq. bilinear_form), on the vector element of   */
+/* Sec. 2.3 (scalar basis times unit vectors).                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Vector element: the scalar basis of `family` (ORC_Q: GLL nodes, GL rule;
+ * ORC_QGLL: GLL nodes and GLL rule) times the unit vectors; DOF (component c,
+ * node i) has local index c * nd + i and value Psi_i e_c.
+ * At a point, with grad u the physical displacement gradient (grad u)_{ca} =
+ * d u_c / d x_a:
+ *   F = I + grad u,  C = F^T F,  E = (C - I) / 2,
+ *   W(E) = lambda/2 tr(E)^2 + mu tr(E E)     (strain energy density),
+ *   S = lambda tr(E) I + 2 mu E              (dW/dE),     P = F S.
+ * mode 0: out[c] = sum_q w_q |det J_q| W(E_q)                (strain energy)
+ * mode 1: out[c][c'*nd + i] = sum_q w |det J| P : grad(Psi_i e_c')
+ *         (the residual form with no body force; du unused)
+ * mode 2: the same test functions against
+ *         dP = dF S + F dS,  dF = grad du,  dE = (dF^T F + F^T dF) / 2,
+ *         dS = lambda tr(dE) I + 2 mu dE
+ *         (the derivative of mode 1 at u0 in the direction du: the bilinear
+ *         form with trial function du and coefficient u0).
+ * u0 and du: [ncells][3 nd].  Trilinear geometry per point.  Returns as
+ * orc_action.
+ */
+static void svk_point(double lambda, double mu, const double H[3][3], const double dH[3][3], int mode,
+                      double *energy, double P[3][3])
+{
+    double F[3][3], E[3][3], S[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) F[a][b] = (a == b ? 1.0 : 0.0) + H[a][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double c = 0.0;
+            for (int k = 0; k < 3; ++k) c += F[k][a] * F[k][b]; /* C = F^T F */
+            E[a][b] = 0.5 * (c - (a == b ? 1.0 : 0.0));
+        }
+    double trE = E[0][0] + E[1][1] + E[2][2];
+    double EE = 0.0; /* tr(E E) */
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) EE += E[a][b] * E[b][a];
+    *energy = 0.5 * lambda * trE * trE + mu * EE;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = (a == b ? lambda * trE : 0.0) + 2.0 * mu * E[a][b];
+    if (mode != 2) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double t = 0.0;
+                for (int k = 0; k < 3; ++k) t += F[a][k] * S[k][b];
+                P[a][b] = t;
+            }
+        return;
+    }
+    double dE[3][3], dS[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += dH[k][a] * F[k][b] + F[k][a] * dH[k][b];
+            dE[a][b] = 0.5 * t;
+        }
+    double trdE = dE[0][0] + dE[1][1] + dE[2][2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) dS[a][b] = (a == b ? lambda * trdE : 0.0) + 2.0 * mu * dE[a][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += dH[a][k] * S[k][b] + F[a][k] * dS[k][b];
+            P[a][b] = t;
+        }
+}
+
+int orc_svk(int family, int degree, int nq1, double lambda, double mu, int mode, long ncells,
+            const double *vertices, const double *u0, const double *du, double *out)
+{
+    if (family != ORC_Q && family != ORC_QGLL) return -2;
+    if (mode < 0 || mode > 2 || (mode == 2 && !du)) return -2;
+    orc_setup s;
+    int rc = setup(family, degree, ORC_LAPLACE, nq1, &s);
+    if (rc) return rc;
+    const int nd = s.e.ndof, nq = s.nq;
+    long bad = -1;
+#pragma omp parallel
+    {
+        double *f = (double *)malloc(sizeof(double) * (size_t)nd * ORC_SLOTS);
+#pragma omp for schedule(dynamic, 4)
+        for (long c = 0; c < ncells; ++c) {
+            const double *X = vertices + c * 24;
+            const double *uc = u0 + (size_t)c * 3 * nd;
+            const double *dc = du ? du + (size_t)c * 3 * nd : 0;
+            double *oc = out + (mode == 0 ? (size_t)c : (size_t)c * 3 * nd);
+            if (mode == 0) oc[0] = 0.0;
+            else
+                for (int i = 0; i < 3 * nd; ++i) oc[i] = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                double xi[3], w, J[3][3], G[3][3];
+                point(&s, q, xi, &w);
+                jacobian(X, xi, J);
+                double det = det3(J);
+                if (det <= 0.0) {
+#pragma omp critical
+                    if (bad < 0 || c < bad) bad = c;
+                }
+                inverse3(J, det, G);
+                /* physical gradients of the scalar basis: f[i*SLOTS + 1 + a] */
+                push_forward(&s.e, s.val + (size_t)q * nd * 3, s.grad + (size_t)q * nd * 9, J, G, det, f);
+                double H[3][3] = {{0}}, dH[3][3] = {{0}};
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int i = 0; i < nd; ++i)
+                        for (int a = 0; a < 3; ++a) {
+                            H[cc][a] += uc[cc * nd + i] * f[i * ORC_SLOTS + 1 + a];
+                            if (dc) dH[cc][a] += dc[cc * nd + i] * f[i * ORC_SLOTS + 1 + a];
+                        }
+                double energy, P[3][3];
+                svk_point(lambda, mu, H, dH, mode, &energy, P);
+                double sc = w * fabs(det);
+                if (mode == 0) {
+                    oc[0] += sc * energy;
+                    continue;
+                }
+                /* P : grad(Psi_i e_cc) = sum_a P[cc][a] d Psi_i / d x_a */
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int i = 0; i < nd; ++i) {
+                        double t = 0.0;
+                        for (int a = 0; a < 3; ++a) t += P[cc][a] * f[i * ORC_SLOTS + 1 + a];
+                        oc[cc * nd + i] += sc * t;
+                    }
+            }
+        }
+        free(f);
+    }
+    teardown(&s);
+    return bad >= 0 ? (int)(1 + (bad > 2000000000L ? 2000000000L : bad)) : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* DOF maps.                                                                */
 /* ------------------------------------------------------------------------ */
 

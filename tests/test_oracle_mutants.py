@@ -1,6 +1,7 @@
 """The oracle's pins catch plausible mistakes.  Each case copies the oracle,
 plants one mistake in the copy's C source (a transposed operand, a wrong index,
-a dropped term, a flipped sign, the wrong Piola map, swapped spaces), and runs
+a dropped term, a flipped sign, the wrong Piola map, swapped spaces, the wrong
+stress or strain product), and runs
 the CPU pin suites against the copy in a subprocess: at least one pin must
 fail.  An unmodified copy must pass the same suites (control).  The mistakes
 are planted only in temporary copies; the repository's oracle is untouched.
@@ -25,8 +26,16 @@ MUTANTS = [
     ("*w = s->wq[q0] * s->wq[q1] * s->wq[q2];", "*w = s->wq[q0] * s->wq[q1] * s->wq[q1];", "weight: wrong index"),
     ("double term = 1.0 / (nodes[i] - nodes[k]);", "double term = 1.0 / (nodes[k] - nodes[i]);",
      "Lagrange derivative: flipped sign"),
+    ("for (int k = 0; k < 3; ++k) t += F[a][k] * S[k][b];", "for (int k = 0; k < 3; ++k) t += S[a][k] * F[k][b];",
+     "SVK: P = S F instead of F S"),
+    ("c += F[k][a] * F[k][b]; /* C = F^T F */", "c += F[a][k] * F[b][k];", "SVK: F F^T instead of F^T F"),
+    ("dS[a][b] = (a == b ? lambda * trdE : 0.0) + 2.0 * mu * dE[a][b];", "dS[a][b] = 2.0 * mu * dE[a][b];",
+     "SVK linearisation: dropped lambda term"),
+    ("t += dH[k][a] * F[k][b] + F[k][a] * dH[k][b];", "t += dH[a][k] * F[b][k] + F[a][k] * dH[b][k];",
+     "SVK linearisation: transposed dE"),
 ]
-PIN_SUITES = [os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_golden.py")]
+PIN_SUITES = [os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_golden.py"),
+              os.path.join(ROOT, "tests", "test_oracle_svk.py")]
 
 
 def run_pins_against_copy(tmp_path, old=None, new=None):

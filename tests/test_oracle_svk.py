@@ -1,0 +1,159 @@
+"""Pins of the oracle's Saint Venant-Kirchhoff hyperelastic forms (strain energy,
+residual, linearised residual on the vector Q_p element) against what the
+mathematics fixes, independently of the oracle's own formulas:
+
+- homogeneous deformations u = A x (exactly in Q_p, also on trilinear cells):
+  energy = volume * W(E) with E, W evaluated here from F = I + A, and the
+  first moments of the residual, sum_i y_(c,i) x_b(node_i) = volume * P_cb;
+- rigid motions u = (R - I) x + t give zero energy and zero residual (frame
+  invariance of E);
+- the residual is the exact directional derivative of the energy, and the
+  linearised residual the exact directional derivative of the residual (the
+  energy is a quartic and the residual a cubic polynomial along a line, so a
+  five-point central difference is exact up to rounding);
+- the linearised residual is symmetric (it is the Hessian of the energy);
+- at u = 0 it is linear elasticity: for linear fields B x and C x the form is
+  volume * (lambda tr B tr C + 2 mu sym(B) : sym(C)).
+
+Volumes come from the trilinear map's own Jacobian evaluated here by exact central
+differences (the map is linear in each reference coordinate) on a 3-point Gauss rule,
+which integrates its polynomial determinant exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_02473_amd import synth
+
+LAM, MU = 1.7, 0.6
+
+
+def corner_map(V, xi):
+    """Physical point of reference point(s) xi under the trilinear vertex map."""
+    xi = np.atleast_2d(xi)
+    x = np.zeros((xi.shape[0], 3))
+    for v in range(8):
+        v0, v1, v2 = v >> 2, (v >> 1) & 1, v & 1
+        phi = ((xi[:, 0] if v0 else 1 - xi[:, 0]) * (xi[:, 1] if v1 else 1 - xi[:, 1])
+               * (xi[:, 2] if v2 else 1 - xi[:, 2]))
+        x += phi[:, None] * V[v][None, :]
+    return x
+
+
+def volume(V):
+    g, w = np.polynomial.legendre.leggauss(3)
+    g, w = 0.5 * (g + 1), 0.5 * w
+    vol = 0.0
+    for a, wa in zip(g, w):
+        for b, wb in zip(g, w):
+            for c, wc in zip(g, w):
+                xi = np.array([a, b, c])
+                J = np.stack([(corner_map(V, xi + 0.25 * e) - corner_map(V, xi - 0.25 * e))[0] / 0.5
+                              for e in np.eye(3)], axis=1)
+                vol += wa * wb * wc * np.linalg.det(J)
+    return vol
+
+
+def node_points(family, p, V):
+    """Physical positions of the scalar element's nodes (GLL), node i = (i0 i1 i2), i2 fastest."""
+    x, _ = oracle.gll_rule(p + 1)
+    xi = np.array([[a, b, c] for a in x for b in x for c in x])
+    return corner_map(V, xi)
+
+
+def linear_field(family, p, V, A, t=None):
+    """Component-major DOFs of u(x) = A x (+ t)."""
+    X = node_points(family, p, V)
+    U = X @ A.T
+    if t is not None:
+        U = U + t
+    return U.T.reshape(-1)
+
+
+def svk_density(F):
+    E = 0.5 * (F.T @ F - np.eye(3))
+    return 0.5 * LAM * np.trace(E) ** 2 + MU * np.trace(E @ E), E
+
+
+def cells(kind, n, seed):
+    return synth.affine_cells(n, seed) if kind == "affine" else synth.trilinear_cells(n, seed)
+
+
+CASES = [("Q", 1, "affine"), ("Q", 2, "trilinear"), ("Q", 3, "affine"), ("QGLL", 2, "trilinear"),
+         ("QGLL", 4, "affine"), ("Q", 4, "trilinear")]
+
+
+@pytest.mark.parametrize("family,p,kind", CASES)
+def test_homogeneous_deformation_energy_and_stress_moments(family, p, kind):
+    V = cells(kind, 3, 40 + p)
+    rng = np.random.default_rng(7 + p)
+    for c in range(3):
+        A = 0.3 * rng.standard_normal((3, 3))
+        u = linear_field(family, p, V[c], A)[None, :]
+        vol = volume(V[c])
+        Wd, E = svk_density(np.eye(3) + A)
+        e = oracle.svk_energy(family, p, V[c:c + 1], u, LAM, MU)[0]
+        assert abs(e - vol * Wd) <= 1e-12 * max(1.0, abs(vol * Wd))
+        F = np.eye(3) + A
+        S = LAM * np.trace(E) * np.eye(3) + 2 * MU * E
+        P = F @ S
+        y = oracle.svk_residual(family, p, V[c:c + 1], u, LAM, MU)[0].reshape(3, -1)
+        X = node_points(family, p, V[c])
+        assert np.allclose(y.sum(axis=1), 0.0, atol=1e-12 * np.abs(P).max())
+        moments = y @ X  # [c][b] = sum_i y_(c,i) x_b(node_i)
+        assert np.allclose(moments, vol * P, rtol=1e-11, atol=1e-12 * np.abs(P).max() * vol)
+
+
+@pytest.mark.parametrize("family,p,kind", CASES)
+def test_rigid_motion_is_stress_free(family, p, kind):
+    V = cells(kind, 2, 50 + p)
+    th = 0.7
+    k = np.array([1.0, -2.0, 0.5]) / np.linalg.norm([1.0, -2.0, 0.5])
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    R = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K
+    u = np.stack([linear_field(family, p, V[c], R - np.eye(3), t=np.array([0.3, -1.0, 2.0])) for c in range(2)])
+    assert np.abs(oracle.svk_energy(family, p, V, u, LAM, MU)).max() <= 1e-13
+    assert np.abs(oracle.svk_residual(family, p, V, u, LAM, MU)).max() <= 1e-12
+
+
+def five_point(f, h=1.0):
+    return (f(-2 * h) - 8 * f(-h) + 8 * f(h) - f(2 * h)) / (12 * h)
+
+
+@pytest.mark.parametrize("family,p,kind", CASES)
+def test_residual_is_energy_derivative_and_jacobian_is_residual_derivative(family, p, kind):
+    V = cells(kind, 4, 60 + p)
+    nd = 3 * (p + 1) ** 3
+    rng = np.random.default_rng(11 + p)
+    u = 0.1 * rng.standard_normal((4, nd))
+    v = 0.1 * rng.standard_normal((4, nd))
+    w = 0.1 * rng.standard_normal((4, nd))
+    r = oracle.svk_residual(family, p, V, u, LAM, MU)
+    dE = five_point(lambda t: oracle.svk_energy(family, p, V, u + t * v, LAM, MU))
+    got = (r * v).sum(axis=1)
+    assert np.allclose(got, dE, rtol=1e-10, atol=1e-12 * np.abs(dE).max())
+    a = oracle.svk_jacobian_action(family, p, V, u, v, LAM, MU)
+    dr = five_point(lambda t: oracle.svk_residual(family, p, V, u + t * v, LAM, MU))
+    assert np.allclose(a, dr, rtol=1e-9, atol=1e-11 * np.abs(dr).max())
+    # symmetry: w . a(u; v) = v . a(u; w)
+    aw = oracle.svk_jacobian_action(family, p, V, u, w, LAM, MU)
+    assert np.allclose((a * w).sum(axis=1), (aw * v).sum(axis=1), rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("family,p,kind", CASES)
+def test_linearisation_at_rest_is_linear_elasticity(family, p, kind):
+    V = cells(kind, 2, 70 + p)
+    rng = np.random.default_rng(13 + p)
+    for c in range(2):
+        B = rng.standard_normal((3, 3))
+        C = rng.standard_normal((3, 3))
+        db = linear_field(family, p, V[c], B)[None, :]
+        dc = linear_field(family, p, V[c], C)[None, :]
+        zero = np.zeros_like(db)
+        a = oracle.svk_jacobian_action(family, p, V[c:c + 1], zero, db, LAM, MU)[0]
+        sB, sC = 0.5 * (B + B.T), 0.5 * (C + C.T)
+        exact = volume(V[c]) * (LAM * np.trace(B) * np.trace(C) + 2 * MU * np.sum(sB * sC))
+        assert abs(a @ dc[0] - exact) <= 1e-11 * max(1.0, abs(exact))
+        # rigid translations are in the kernel of the linearised form at rest
+        t = linear_field(family, p, V[c], np.zeros((3, 3)), t=np.array([1.0, 2.0, -3.0]))[None, :]
+        assert np.abs(oracle.svk_jacobian_action(family, p, V[c:c + 1], zero, t, LAM, MU)).max() <= 1e-12
