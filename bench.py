@@ -62,10 +62,11 @@ def main():
                          "every degree now; 'off' keeps the library defaults")
     ap.add_argument("--no-tune", dest="tune", action="store_const", const="off", help="same as --tune off")
     ap.add_argument("--save-tuning", default="", help="write the tuning choices used to this JSON file")
-    ap.add_argument("--legs", default="mass,collocated,trilinear,global,vec,matrix,batch",
+    ap.add_argument("--legs", default="mass,collocated,trilinear,svk,global,vec,matrix,batch",
                     help="side measurements beside the headline: mass (Q_p mass action, 64^3), collocated "
                          "(Laplace action with the GLL rule, B = I, 64^3), trilinear (Laplace action on general "
-                         "trilinear cells, per-point geometry, 64^3 cells), global (the "
+                         "trilinear cells, per-point geometry, 64^3 cells), svk (Saint Venant-Kirchhoff "
+                         "linearised residual on vector Q_p, 64^3 cells), global (the "
                          "assembled C0 Q_p Laplace action on global vectors, 64^3), vec (NCF/NCE "
                          "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
                          "launch); '' = none")
@@ -182,6 +183,8 @@ def main():
                                                   family="QGLL", form="LAPLACE")
     if "trilinear" in legs:
         side["trilinear_laplace"] = trilinear_leg(sf, V.shape[0], degrees, bufs, args.steps, stream)
+    if "svk" in legs:
+        side["svk_hyperelastic"] = svk_leg(sf, ctx, V, degrees, args.steps, stream)
     if "global" in legs:
         side["global_action"] = global_leg(sf, ctx, V, bufs, degrees, glob, args.steps, stream)
     if "vec" in legs:
@@ -326,6 +329,38 @@ def trilinear_leg(sf, ncells, degrees, bufs, reps, stream):
         del y
     assert sf.sf_check_errors(c) == 0
     c.close()
+    return out
+
+
+def svk_leg(sf, ctx, V, degrees, reps, stream, lam=1.3, mu=0.8):
+    """Saint Venant-Kirchhoff hyperelastic operator on the vector Q_p element (3 (p+1)^3 DOFs
+    per cell), 64^3 box cells: the linearised residual at u0 applied to du (SF_SVK), u0 =
+    0.01 N(0,1), du N(0,1), drawn on the GPU.  Algorithmic bytes per cell: u0, du and y,
+    3 n^3 FP64 each, plus 192 B of vertices.  Inputs are rotated between two copies when
+    one set would fit the 256 MB last-level cache."""
+    import torch
+
+    from paper_1711_02473_amd import synth
+
+    ncells = V.shape[0]
+    out = {}
+    for p in degrees:
+        n3 = (p + 1) ** 3
+        op = sf.make_op("Q", p, "SVK", alpha=lam, beta=mu)
+        sets = [synth.device_displacements(ncells, 3 * n3, 1, p)]
+        if ncells * 3 * n3 * 8 * 3 < (1 << 30):
+            sets.append(synth.device_displacements(ncells, 3 * n3, 2, p))
+        y = torch.empty_like(sets[0][1])
+        sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], y, stream)
+        ms = timed(lambda it: sf.assemble_action(ctx, op, ncells, V, sets[it % len(sets)][0], sets[it % len(sets)][1],
+                                                 y, stream), reps, stream)
+        nbytes = ncells * (3 * 3 * n3 * 8 + 192)
+        gbs = nbytes / (ms / 1e3) / 1e9
+        out[str(p)] = {"ms": round(ms, 4), "gdofs_local": round(ncells * 3 * n3 / (ms / 1e3) / 1e9, 3),
+                       "gdofs_global": round(3 * (64 * p + 1) ** 3 / (ms / 1e3) / 1e9, 3),
+                       "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+        del sets, y
+    assert sf.sf_check_errors(ctx) == 0
     return out
 
 

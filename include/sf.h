@@ -78,7 +78,27 @@ extern "C" {
  * variant (Sec. 2.5).  Its mass matrix is diagonal (lumped); the 1-D stiffness
  * is still integrated exactly.  kappa is given at the GLL points. */
 enum { SF_Q = 0, SF_DQ = 1, SF_NCF = 2, SF_NCE = 3, SF_QGLL = 4 };
-enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3 };
+enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3, SF_SVK = 4, SF_SVK_RESIDUAL = 5 };
+/* SF_SVK / SF_SVK_RESIDUAL: the Saint Venant-Kirchhoff hyperelastic model of
+ * the paper's evaluation on the VECTOR Q_p element (family SF_Q, or SF_QGLL
+ * for its GLL-collocated variant; p = 1..8): the scalar basis times the unit
+ * vectors (Sec. 2.3), ndof_cell = 3 (p+1)^3, local DOF (component c, node i)
+ * at c (p+1)^3 + i (component-major; node numbering as for the scalar
+ * element).  op.alpha = lambda, op.beta = mu (the Lame parameters).  With
+ * F = I + grad u, E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E, P = F S:
+ *   SF_SVK_RESIDUAL  y_(c,i) = int P(u) : grad(Psi_i e_c)  (residual form,
+ *                    no body force; `u` is the displacement, kappa NULL);
+ *   SF_SVK           y_(c,i) = int dP(u0; du) : grad(Psi_i e_c), the
+ *                    linearised residual (eq. bilinear_form) applied to the
+ *                    direction du = `u`, with dF = grad du,
+ *                    dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE,
+ *                    dP = dF S + F dS; the linearisation point u0 is passed
+ *                    in `kappa` (the form's coefficient) as a local vector of
+ *                    the same layout, NULL for u0 = 0 (linear elasticity).
+ * Quadrature: p+1 points per axis (GL for SF_Q, GLL for SF_QGLL).  FP64
+ * contractions and SF_F64 storage only; action only (element matrices
+ * return SF_ERR_UNSUPPORTED).  Geometry: affine cells, or any trilinear cell
+ * under SF_GEOM_TRILINEAR (J per point). */
 /* contraction precision: FP64, FP32 (both VALU); BF16 / FP16 single-term MFMA
  * with FP32 accumulation; BF16X3 = operands split into three BF16 terms
  * (hi + mid + lo), six cross products per contraction, FP32 accumulation.
@@ -167,7 +187,8 @@ int sf_element_dims(const sf_op *op, int32_t *ndof_cell, int32_t *nq_cell);
  * Operator action, the matrix-free linear form (Sec. 1.1; Sec. 3.3,
  * eq. coeff_eval and eq. form_eval):  y[c][i] = a(psi_i, u_c) on every cell.
  *   vertices  device, [ncells][8][3] FP64
- *   kappa     device, [ncells][nq_cell] io_dtype, or NULL (kappa = 1)
+ *   kappa     device, [ncells][nq_cell] io_dtype, or NULL (kappa = 1);
+ *             SF_SVK: u0 [ncells][ndof_cell] or NULL; SF_SVK_RESIDUAL: NULL
  *   u         device, [ncells][ndof_cell] io_dtype, cell-major local vector
  *   y         device, [ncells][ndof_cell] io_dtype, overwritten; must not
  *             alias u or kappa
@@ -218,7 +239,8 @@ int64_t sf_concat_index(int32_t ndim, int32_t nblocks, const int32_t *extents, i
 
 /* Host only.  Per-block extents of the element of `op` (family and degree):
  * *nblocks in {1,3}; extents[b*3+a] functions of block b along axis a;
- * offsets[b] the block's first local index. */
+ * offsets[b] the block's first local index (the vector element of SF_SVK:
+ * three blocks of (p+1)^3, one per component). */
 int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t *offsets);
 
 /*

@@ -22,8 +22,11 @@ struct Dims {
 bool scalar_family(int family) { return family == SF_Q || family == SF_DQ || family == SF_QGLL; }
 int degree_max(int family) { return scalar_family(family) ? 8 : 6; }
 
+bool svk_form(int form) { return form == SF_SVK || form == SF_SVK_RESIDUAL; }
+
 bool form_ok(int family, int form)
 {
+    if (svk_form(form)) return family == SF_Q || family == SF_QGLL;
     if (scalar_family(family)) return form == SF_MASS || form == SF_LAPLACE;
     if (family == SF_NCF) return form == SF_MASS || form == SF_HDIV;
     if (family == SF_NCE) return form == SF_MASS || form == SF_HCURL;
@@ -44,13 +47,14 @@ int check_op(const sf_op *op, Dims *d)
     const int p = op->degree;
     const int nq1 = op->nq1 ? op->nq1 : p + 1;
     if (nq1 != p + 1) return SF_ERR_UNSUPPORTED; // kernels are built for p+1 Gauss points per axis
+    if (svk_form(op->form) && (op->precision != SF_FP64 || op->io_dtype != SF_F64)) return SF_ERR_UNSUPPORTED;
     Dims r;
     r.nq1 = nq1;
     r.nq = nq1 * nq1 * nq1;
     if (scalar_family(op->family)) {
         r.n0 = p + 1;
         r.n1 = 0;
-        r.ndof = (p + 1) * (p + 1) * (p + 1);
+        r.ndof = (svk_form(op->form) ? 3 : 1) * (p + 1) * (p + 1) * (p + 1);
     } else {
         r.n0 = p + 1; // P_k factor
         r.n1 = p;     // dP_{k-1} factor
@@ -370,6 +374,11 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     if (rc) return rc;
     a.u = u;
     a.y = y;
+    if (svk_form(op->form)) {
+        if (op->form == SF_SVK_RESIDUAL && kappa) return SF_ERR_ARG;
+        a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
+        return launch_action_svk(a);
+    }
     if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
         return launch_action_mixed(a);
     if (scalar_family(op->family)) {
@@ -419,7 +428,7 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
     Dims d;
     int rc = check_op(op, &d);
     if (rc) return rc;
-    if (op->precision != SF_FP64) return SF_ERR_UNSUPPORTED;
+    if (op->precision != SF_FP64 || svk_form(op->form)) return SF_ERR_UNSUPPORTED;
     if (ncells == 0) return SF_OK;
     if (!vertices || !A || A == kappa) return SF_ERR_ARG;
     LaunchArgs a;
@@ -480,6 +489,14 @@ int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t
     if (rc) return rc;
     if (!nblocks || !extents || !offsets) return SF_ERR_ARG;
     const int p = op->degree;
+    if (svk_form(op->form)) { // vector element: one scalar block per component
+        *nblocks = 3;
+        for (int c = 0; c < 3; ++c) {
+            extents[c * 3] = extents[c * 3 + 1] = extents[c * 3 + 2] = p + 1;
+            offsets[c] = c * (p + 1) * (p + 1) * (p + 1);
+        }
+        return SF_OK;
+    }
     if (scalar_family(op->family)) {
         *nblocks = 1;
         extents[0] = extents[1] = extents[2] = p + 1;

@@ -1,0 +1,402 @@
+// Saint Venant-Kirchhoff hyperelasticity on the vector Q_p element (the
+// hyperelastic model of the paper's evaluation; vector element of Sec. 2.3),
+// matrix-free, FP64, on gfx950.
+//
+// Vector element: the scalar Q_p basis (GLL nodes) times the unit vectors,
+// local DOF (component c, node i) at c * n^3 + i.  Because every vector
+// basis function has a single nonzero component (Psi_(i,c) = Psi_i e_c, the
+// Kronecker-delta structure of Sec. 2.3), the tested flux separates by
+// component: y_(c,i) = sum_q sum_d dPsi_i/dxi_d (q) phi_(c,d)(q), one scalar
+// backward contraction chain per component (delta cancellation, Sec. 3.4).
+//
+// Per point, with grad u = (reference gradient) G, G = J^{-1}:
+//   F = I + grad u,  E = (F^T F - I) / 2,  S = lambda tr(E) I + 2 mu E,
+//   residual form:   P = F S
+//   linearised form: dF = grad du, dE = (dF^T F + F^T dF) / 2,
+//                    dS = lambda tr(dE) I + 2 mu dE,  P = dF S + F dS,
+// and the reference flux phi = w |det J| P G^T.
+//
+// Method: sum factorisation with the collocated derivative, as in the scalar
+// actions (Sec. 3.3, eq. coeff_eval / eq. form_eval): every field is
+// interpolated to the Gauss points with B one axis at a time (skipped for the
+// GLL-collocated variant, B = I, Sec. 2.5), differentiated with the
+// collocation matrix Dh along each axis, combined pointwise, and brought back
+// with Dh^T (summed over the three directions) and B^T.
+//
+// Mapping: one workgroup owns C cells and keeps every per-cell tensor in LDS
+// (3 per interpolated field: the values, overwritten by the axis-0 derivative,
+// and the axis-1 and axis-2 derivatives).  The linearised form interpolates
+// six fields (u0 and du), the residual three.  Inputs and outputs move
+// between HBM and LDS with linear, fully coalesced copies; each contraction
+// stage gives a thread one pencil (a line of one tensor along one axis) and
+// applies the even-odd form of the 1-D matrix in registers.
+#include "sf_device.hpp"
+#include "sf_internal.hpp"
+
+namespace sf {
+
+template <int N, bool JAC> struct SvkShape {
+    using L = Lds3<N>;
+    static constexpr int NF = JAC ? 6 : 3; // interpolated fields
+    static constexpr int NS = 3 * NF;      // LDS tensors per cell
+    static constexpr int GEO = 24;         // per-cell geometry: vertices, or G (9) and det J
+    static constexpr int CELL = NS * L::CS + GEO;
+    static constexpr int C = (8192 / CELL) > 0 ? 8192 / CELL : 1; // about 64 KB of tensors per group
+    static constexpr int NT = 256; // the kernel's launch bound
+};
+
+// Loop over the C * NF * N * N pencils along one axis of field tensors
+// (slot 3 f + SLOT of every cell): f(cell, field, a, b).
+template <int N, int C, int NF, int NT, typename Fn> __device__ __forceinline__ void svk_pencils(Fn &&fn)
+{
+    constexpr int NP = N * N, PER = NF * NP;
+    for (int t = threadIdx.x; t < C * PER; t += NT) {
+        const int c = t / PER;
+        const int r = t - c * PER;
+        const int f = r / NP;
+        const int p = r - f * NP;
+        const int a = p / N;
+        fn(c, f, a, p - a * N);
+    }
+}
+
+// Pointwise stage: reference gradients gu (u0, or the displacement) and gd
+// (du) at one point -> reference flux w |det J| P G^T, returned in gu.
+template <bool JAC>
+__device__ __forceinline__ void svk_point(double (&gu)[3][3], const double (&gd)[3][3], const double (&G)[3][3],
+                                          double wdet, double lambda, double mu)
+{
+    double F[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            double h = gu[c][0] * G[0][e];
+            h = fma(gu[c][1], G[1][e], h);
+            h = fma(gu[c][2], G[2][e], h);
+            F[c][e] = (c == e ? 1.0 : 0.0) + h;
+        }
+    double S[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            double t = F[0][a] * F[0][b];
+            t = fma(F[1][a], F[1][b], t);
+            t = fma(F[2][a], F[2][b], t);
+            S[a][b] = 0.5 * (t - (a == b ? 1.0 : 0.0)); // E
+        }
+    const double ltr = lambda * (S[0][0] + S[1][1] + S[2][2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            S[a][b] = 2.0 * mu * S[a][b] + (a == b ? ltr : 0.0);
+            S[b][a] = S[a][b];
+        }
+    double P[3][3];
+    if constexpr (!JAC) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) P[c][e] = F[c][0] * S[0][e] + F[c][1] * S[1][e] + F[c][2] * S[2][e];
+    } else {
+        double dF[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                double h = gd[c][0] * G[0][e];
+                h = fma(gd[c][1], G[1][e], h);
+                dF[c][e] = fma(gd[c][2], G[2][e], h);
+            }
+        double dS[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t += dF[k][a] * F[k][b] + F[k][a] * dF[k][b];
+                dS[a][b] = 0.5 * t; // dE
+            }
+        const double ldtr = lambda * (dS[0][0] + dS[1][1] + dS[2][2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                dS[a][b] = 2.0 * mu * dS[a][b] + (a == b ? ldtr : 0.0);
+                dS[b][a] = dS[a][b];
+            }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t += dF[c][k] * S[k][e] + F[c][k] * dS[k][e];
+                P[c][e] = t;
+            }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gu[c][d] = wdet * (P[c][0] * G[d][0] + P[c][1] * G[d][1] + P[c][2] * G[d][2]);
+}
+
+template <int N, bool COLL, bool JAC, bool TRI>
+__global__ void __launch_bounds__(256)
+    svk_action_kernel(const int64_t ncells, const double *__restrict__ vert, const double *__restrict__ f0,
+                      const double *__restrict__ f1, double *__restrict__ y, const double *__restrict__ tab,
+                      const double lambda, const double mu, int *__restrict__ err)
+{
+    using Sh = SvkShape<N, JAC>;
+    using L = Lds3<N>;
+    constexpr int C = Sh::C, NF = Sh::NF, NS = Sh::NS, NT = Sh::NT, N3 = N * N * N;
+    constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
+    constexpr TabLayout TL(N, 0, N);
+    __shared__ double smem[C * Sh::CELL];
+    double *geo = smem;            // [C][GEO]
+    double *ts = smem + C * Sh::GEO; // [C][NS][CS], field f: slots 3f (values / d0), 3f+1 (d1), 3f+2 (d2)
+    auto tensor = [&](int c, int s) { return ts + (c * NS + s) * CS; };
+    const int64_t cell0 = int64_t(blockIdx.x) * C;
+
+    // geometry; padding cells get the unit cube
+    if constexpr (TRI) {
+        for (int t = threadIdx.x; t < C * 24; t += NT) {
+            const int c = t / 24, k = t - c * 24;
+            const int v = k / 3, ax = k - v * 3;
+            const double unit = ((v >> (2 - ax)) & 1) ? 1.0 : 0.0;
+            geo[t] = (cell0 + c < ncells) ? vert[(cell0 + c) * 24 + k] : unit;
+        }
+    } else {
+        if (threadIdx.x < C) {
+            const int c = threadIdx.x;
+            double J[3][3], G[3][3], det = 1.0;
+            if (cell0 + c < ncells) {
+                const int fl = affine_jacobian(vert + (cell0 + c) * 24, J, det);
+                if (fl) atomicOr(err, fl);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+            }
+            inverse3(J, det, G);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) geo[c * Sh::GEO + 3 * a + b] = G[a][b];
+            geo[c * Sh::GEO + 9] = fabs(det);
+        }
+    }
+    // fields: f < 3 component f of f0, f >= 3 component f - 3 of f1 (zero when the array is NULL)
+    for (int t = threadIdx.x; t < C * NF * N3; t += NT) {
+        const int c = t / (NF * N3);
+        const int r = t - c * NF * N3;
+        const int f = r / N3;
+        const int i = r - f * N3;
+        const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
+        const double *src = f < 3 ? f0 : f1;
+        double v = 0.0;
+        if (src != nullptr && cell0 + c < ncells) v = src[(cell0 + c) * (3 * N3) + (f % 3) * N3 + i];
+        tensor(c, 3 * f)[i0 * S1 + i1 * S2 + i2] = v;
+    }
+    __syncthreads();
+
+    // interpolation to the Gauss points, one axis at a time, in place
+    if constexpr (!COLL) {
+        const double *BE = tab + TL.BEO();
+        svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+            apply_eo<N, false, false>(BE, x, o);
+            st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+        });
+        __syncthreads();
+        svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+            apply_eo<N, false, false>(BE, x, o);
+            st_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+        });
+        __syncthreads();
+        svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+            apply_eo<N, false, false>(BE, x, o);
+            st_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+        });
+        __syncthreads();
+    }
+    // reference gradients: axes 1 and 2 into their own tensors, then axis 0 in place
+    const double *DE = tab + TL.DhEO();
+    svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+        double x[N], o[N];
+        ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+        apply_eo<N, true, false>(DE, x, o);
+        st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
+    });
+    svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+        double x[N], o[N];
+        ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+        apply_eo<N, true, false>(DE, x, o);
+        st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, o);
+    });
+    __syncthreads();
+    svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+        double x[N], o[N];
+        ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+        apply_eo<N, true, false>(DE, x, o);
+        st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+    });
+    __syncthreads();
+
+    // pointwise: flux of component c along reference direction d into slot 3c + d
+    {
+        const double *W = tab + TL.W();
+        const double *XQ = tab + TL.XQ();
+        int bad = 0;
+        for (int t = threadIdx.x; t < C * N3; t += NT) {
+            const int c = t / N3;
+            const int i = t - c * N3;
+            const int q0 = i / (N * N), q1 = (i / N) % N, q2 = i % N;
+            const int o = q0 * S1 + q1 * S2 + q2;
+            double gu[3][3], gd[3][3], G[3][3], wdet;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    gu[k][d] = tensor(c, 3 * k + d)[o];
+                    if constexpr (JAC) gd[k][d] = tensor(c, 9 + 3 * k + d)[o];
+                    else gd[k][d] = 0.0;
+                }
+            const double w = W[q0] * W[q1] * W[q2];
+            if constexpr (TRI) {
+                double J[3][3];
+                const double det = trilinear_jacobian(geo + c * Sh::GEO, XQ[q0], XQ[q1], XQ[q2], J);
+                if (!(det > 0.0) && cell0 + c < ncells) bad = SF_FLAG_DETJ;
+                inverse3(J, det, G);
+                wdet = w * fabs(det);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) G[a][b] = geo[c * Sh::GEO + 3 * a + b];
+                wdet = w * geo[c * Sh::GEO + 9];
+            }
+            svk_point<JAC>(gu, gd, G, wdet, lambda, mu);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) tensor(c, 3 * k + d)[o] = gu[k][d];
+        }
+        if (bad) atomicOr(err, bad);
+    }
+    __syncthreads();
+
+    // back to the DOFs: Dh^T along axes 1 and 2 in place, then along axis 0 with the
+    // three directions summed (and B^T applied on the same pencil), then B^T along 1, 2
+    const double *DTE = tab + TL.DhTEO();
+    svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+        double x[N], o[N];
+        ld_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
+        apply_eo<N, true, false>(DTE, x, o);
+        st_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+    });
+    svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+        double x[N], o[N];
+        ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+        apply_eo<N, true, false>(DTE, x, o);
+        st_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, o);
+    });
+    __syncthreads();
+    const double *BTE = tab + TL.BTEO();
+    svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+        double x[N], o[N];
+        ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+        ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+        apply_eo<N, true, true>(DTE, x, o);
+        ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+#pragma unroll
+        for (int j = 0; j < N; ++j) o[j] += x[j];
+        if constexpr (!COLL) {
+            apply_eo<N, false, false>(BTE, o, x);
+            st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+        } else {
+            st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+        }
+    });
+    __syncthreads();
+    if constexpr (!COLL) {
+        svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+            apply_eo<N, false, false>(BTE, x, o);
+            st_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+        });
+        __syncthreads();
+        svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+            apply_eo<N, false, false>(BTE, x, o);
+            st_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+        });
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < C * 3 * N3; t += NT) {
+        const int c = t / (3 * N3);
+        const int r = t - c * 3 * N3;
+        const int k = r / N3;
+        const int i = r - k * N3;
+        const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
+        if (cell0 + c < ncells) y[(cell0 + c) * (3 * N3) + r] = tensor(c, 3 * k)[i0 * S1 + i1 * S2 + i2];
+    }
+}
+
+namespace {
+
+template <int N, bool COLL, bool JAC, bool TRI> int launch_svk4(const LaunchArgs &a)
+{
+    using Sh = SvkShape<N, JAC>;
+    const int64_t groups = (a.ncells + Sh::C - 1) / Sh::C;
+    if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
+    const double *f0 = JAC ? static_cast<const double *>(a.kappa) : static_cast<const double *>(a.u);
+    const double *f1 = JAC ? static_cast<const double *>(a.u) : nullptr;
+    hipLaunchKernelGGL((svk_action_kernel<N, COLL, JAC, TRI>), dim3(unsigned(groups)), dim3(Sh::NT), 0, a.stream,
+                       a.ncells, a.vert, f0, f1, static_cast<double *>(a.y), a.tab64, a.alpha, a.beta, a.err);
+    return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+template <int N> int launch_svk_n(const LaunchArgs &a)
+{
+    const bool coll = a.family == SF_QGLL;
+    const bool jac = a.form == SF_SVK;
+    if (coll) {
+        if (jac) return a.trilinear ? launch_svk4<N, true, true, true>(a) : launch_svk4<N, true, true, false>(a);
+        return a.trilinear ? launch_svk4<N, true, false, true>(a) : launch_svk4<N, true, false, false>(a);
+    }
+    if (jac) return a.trilinear ? launch_svk4<N, false, true, true>(a) : launch_svk4<N, false, true, false>(a);
+    return a.trilinear ? launch_svk4<N, false, false, true>(a) : launch_svk4<N, false, false, false>(a);
+}
+
+} // namespace
+
+int launch_action_svk(const LaunchArgs &a)
+{
+    if (a.nq != a.degree + 1 || a.precision != SF_FP64 || a.io != SF_F64) return SF_ERR_UNSUPPORTED;
+    if (a.family != SF_Q && a.family != SF_QGLL) return SF_ERR_UNSUPPORTED;
+    switch (a.degree + 1) {
+    case 2: return launch_svk_n<2>(a);
+    case 3: return launch_svk_n<3>(a);
+    case 4: return launch_svk_n<4>(a);
+    case 5: return launch_svk_n<5>(a);
+    case 6: return launch_svk_n<6>(a);
+    case 7: return launch_svk_n<7>(a);
+    case 8: return launch_svk_n<8>(a);
+    case 9: return launch_svk_n<9>(a);
+    default: return SF_ERR_UNSUPPORTED;
+    }
+}
+
+} // namespace sf

@@ -126,6 +126,26 @@ def device_action_inputs(ncells, n3, config_id, degree, nsets=1):
     return out
 
 
+def displacements(ncells, ndof, config_id, amp=0.01):
+    """Host-side displacement pair (u0, du) for the hyperelastic forms, [ncells][ndof] each:
+    u0 = amp N(0, 1) (the linearisation point), du N(0, 1) (the direction); stream 2."""
+    g = rng(config_id, 2)
+    u0 = amp * g.standard_normal((ncells, ndof))
+    du = g.standard_normal((ncells, ndof))
+    return u0, du
+
+
+def device_displacements(ncells, ndof, config_id, degree, amp=0.01):
+    """Full-size (u0, du) on "cuda" from torch's generator seeded with (config_id, degree):
+    u0 = amp N(0, 1), du N(0, 1), [ncells][ndof] FP64."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SEED * 1000 + int(config_id) * 100 + 20 + int(degree))
+    u0 = torch.randn((ncells, ndof), generator=g, device="cuda", dtype=torch.float64) * amp
+    du = torch.randn((ncells, ndof), generator=g, device="cuda", dtype=torch.float64)
+    return u0, du
+
+
 def device_kappa(ncells, nq, config_id, degree):
     """kappa U[0.5, 2], [ncells][nq] FP64 on "cuda", from torch's generator seeded with
     (config_id, degree) (stream 1 of the recipe)."""

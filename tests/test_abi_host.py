@@ -134,3 +134,20 @@ def test_plan_axis_order_is_cheapest():
             costs[perm] = f
         assert flops == min(costs.values()) == costs[tuple(order)]
         assert tuple(order) == min(p for p, c in costs.items() if c == flops)
+
+
+def test_svk_vector_element_dims_layout_and_validation():
+    """The hyperelastic forms act on the vector Q_p element: 3 (p+1)^3 DOFs in three
+    component blocks; FP64 only, family Q or QGLL only, no element matrices."""
+    for fam in ("Q", "QGLL"):
+        for p in range(1, 9):
+            for form in ("SVK", "SVK_RESIDUAL"):
+                op = sf.make_op(fam, p, form, alpha=1.0, beta=0.5)
+                n = p + 1
+                assert sf.sf_element_dims(op) == (3 * n ** 3, n ** 3)
+                ext, off = sf.sf_block_layout(op)
+                assert ext == [[n, n, n]] * 3 and off == [0, n ** 3, 2 * n ** 3]
+    for bad in (sf.make_op("DQ", 2, "SVK"), sf.make_op("NCF", 2, "SVK"), sf.make_op("Q", 2, "SVK", precision="fp32"),
+                sf.make_op("Q", 2, "SVK", io="f32"), sf.make_op("Q", 9, "SVK"), sf.make_op("Q", 2, "SVK", nq1=4)):
+        with pytest.raises(sf.SfError):
+            sf.sf_element_dims(bad)
