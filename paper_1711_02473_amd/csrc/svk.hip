@@ -35,14 +35,18 @@
 
 namespace sf {
 
+// threads per workgroup: 512 where one cell's eighteen tensors fill most of
+// the LDS (one workgroup per CU), so that the CU still holds eight waves
+__host__ __device__ constexpr int svk_nt(int n, bool jac) { return (jac && n >= 8) ? 512 : 256; }
+
 template <int N, bool JAC> struct SvkShape {
     using L = Lds3<N>;
     static constexpr int NF = JAC ? 6 : 3; // interpolated fields
     static constexpr int NS = 3 * NF;      // LDS tensors per cell
-    static constexpr int GEO = 24;         // per-cell geometry: vertices, or G (9) and det J
+    static constexpr int GEO = 34;         // per-cell geometry: vertices (24), G (9), |det J|
     static constexpr int CELL = NS * L::CS + GEO;
     static constexpr int C = (8192 / CELL) > 0 ? 8192 / CELL : 1; // about 64 KB of tensors per group
-    static constexpr int NT = 256; // the kernel's launch bound
+    static constexpr int NT = svk_nt(N, JAC);
 };
 
 // Loop over the C * NF * N * N pencils along one axis of field tensors
@@ -57,6 +61,25 @@ template <int N, int C, int NF, int NT, typename Fn> __device__ __forceinline__ 
         const int p = r - f * NP;
         const int a = p / N;
         fn(c, f, a, p - a * N);
+    }
+}
+
+// Two independent pencil stages over the same fields, one along axis 1 (f1) and
+// one along axis 2 (f2), run as one loop so that all threads have work.
+template <int N, int C, int NF, int NT, typename F1, typename F2>
+__device__ __forceinline__ void svk_pencils_12(F1 &&f1, F2 &&f2)
+{
+    constexpr int NP = N * N, PER = NF * NP, TOT = C * PER;
+    for (int t = threadIdx.x; t < 2 * TOT; t += NT) {
+        const bool second = t >= TOT;
+        const int u = second ? t - TOT : t;
+        const int c = u / PER;
+        const int r = u - c * PER;
+        const int f = r / NP;
+        const int p = r - f * NP;
+        const int a = p / N;
+        if (second) f2(c, f, a, p - a * N);
+        else f1(c, f, a, p - a * N);
     }
 }
 
@@ -145,7 +168,7 @@ __device__ __forceinline__ void svk_point(double (&gu)[3][3], const double (&gd)
 }
 
 template <int N, bool COLL, bool JAC, bool TRI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(svk_nt(N, JAC))
     svk_action_kernel(const int64_t ncells, const double *__restrict__ vert, const double *__restrict__ f0,
                       const double *__restrict__ f1, double *__restrict__ y, const double *__restrict__ tab,
                       const double lambda, const double mu, int *__restrict__ err)
@@ -155,202 +178,236 @@ __global__ void __launch_bounds__(256)
     constexpr int C = Sh::C, NF = Sh::NF, NS = Sh::NS, NT = Sh::NT, N3 = N * N * N;
     constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
     constexpr TabLayout TL(N, 0, N);
+    // inputs of one group: C * NF * N3 field values, then C * 24 vertex coordinates
+    constexpr int NFLD = C * NF * N3, NIN = NFLD + C * 24, K = (NIN + NT - 1) / NT;
     __shared__ double smem[C * Sh::CELL];
-    double *geo = smem;            // [C][GEO]
+    double *geo = smem;              // [C][GEO]: vertices (24), G (9), |det J|
     double *ts = smem + C * Sh::GEO; // [C][NS][CS], field f: slots 3f (values / d0), 3f+1 (d1), 3f+2 (d2)
     auto tensor = [&](int c, int s) { return ts + (c * NS + s) * CS; };
-    const int64_t cell0 = int64_t(blockIdx.x) * C;
+    const int64_t ngroups = (ncells + C - 1) / C;
 
-    // geometry; padding cells get the unit cube
-    if constexpr (TRI) {
-        for (int t = threadIdx.x; t < C * 24; t += NT) {
-            const int c = t / 24, k = t - c * 24;
-            const int v = k / 3, ax = k - v * 3;
-            const double unit = ((v >> (2 - ax)) & 1) ? 1.0 : 0.0;
-            geo[t] = (cell0 + c < ncells) ? vert[(cell0 + c) * 24 + k] : unit;
+    // This thread's share of a group's inputs, requested in one unrolled batch
+    // (every lane loads; lanes without an element read vert[0] and discard it).
+    // Fields f < 3 are component f of f0, f >= 3 component f - 3 of f1 (zero when
+    // the array is NULL); padding cells get zero fields and the unit cube.
+    double pf[K];
+    auto fetch = [&](int64_t g) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int t = threadIdx.x + k * NT;
+            const double *src = vert;
+            double fill = 0.0;
+            bool ok = false;
+            if (t < NFLD) {
+                const int c = t / (NF * N3);
+                const int r = t - c * NF * N3;
+                const int f = r / N3;
+                const double *base = f < 3 ? f0 : f1;
+                ok = base != nullptr && g * C + c < ncells;
+                if (ok) src = base + (g * C + c) * (3 * N3) + (f % 3) * N3 + (r - f * N3);
+            } else if (t < NIN) {
+                const int c = (t - NFLD) / 24, e = (t - NFLD) - c * 24;
+                const int v = e / 3, ax = e - v * 3;
+                fill = ((v >> (2 - ax)) & 1) ? 1.0 : 0.0;
+                ok = g * C + c < ncells;
+                if (ok) src = vert + (g * C + c) * 24 + e;
+            }
+            const double x = *src;
+            pf[k] = ok ? x : fill;
         }
-    } else {
-        if (threadIdx.x < C) {
-            const int c = threadIdx.x;
-            double J[3][3], G[3][3], det = 1.0;
-            if (cell0 + c < ncells) {
-                const int fl = affine_jacobian(vert + (cell0 + c) * 24, J, det);
-                if (fl) atomicOr(err, fl);
-            } else {
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int t = threadIdx.x + k * NT;
+            if (t < NFLD) {
+                const int c = t / (NF * N3);
+                const int r = t - c * NF * N3;
+                const int f = r / N3;
+                const int i = r - f * N3;
+                const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
+                tensor(c, 3 * f)[i0 * S1 + i1 * S2 + i2] = pf[k];
+            } else if (t < NIN) {
+                const int c = (t - NFLD) / 24;
+                geo[c * Sh::GEO + (t - NFLD - c * 24)] = pf[k];
+            }
+        }
+    };
+
+    // persistent workgroups: group g + gridDim.x is requested while g is computed
+    int64_t g = blockIdx.x;
+    if (g < ngroups) fetch(g);
+    for (; g < ngroups; g += gridDim.x) {
+        const int64_t cell0 = g * C;
+        stash();
+        if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+        __syncthreads();
+        if constexpr (!TRI) { // affine cells: G and |det J| once per cell
+            if (threadIdx.x < C) {
+                const int c = threadIdx.x;
+                double J[3][3], G[3][3], det = 1.0;
+                const int fl = affine_jacobian(geo + c * Sh::GEO, J, det);
+                if (fl && cell0 + c < ncells) atomicOr(err, fl);
+                inverse3(J, det, G);
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+                    for (int b = 0; b < 3; ++b) geo[c * Sh::GEO + 24 + 3 * a + b] = G[a][b];
+                geo[c * Sh::GEO + 33] = fabs(det);
             }
-            inverse3(J, det, G);
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) geo[c * Sh::GEO + 3 * a + b] = G[a][b];
-            geo[c * Sh::GEO + 9] = fabs(det);
         }
-    }
-    // fields: f < 3 component f of f0, f >= 3 component f - 3 of f1 (zero when the array is NULL)
-    for (int t = threadIdx.x; t < C * NF * N3; t += NT) {
-        const int c = t / (NF * N3);
-        const int r = t - c * NF * N3;
-        const int f = r / N3;
-        const int i = r - f * N3;
-        const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
-        const double *src = f < 3 ? f0 : f1;
-        double v = 0.0;
-        if (src != nullptr && cell0 + c < ncells) v = src[(cell0 + c) * (3 * N3) + (f % 3) * N3 + i];
-        tensor(c, 3 * f)[i0 * S1 + i1 * S2 + i2] = v;
-    }
-    __syncthreads();
 
-    // interpolation to the Gauss points, one axis at a time, in place
-    if constexpr (!COLL) {
-        const double *BE = tab + TL.BEO();
+        // interpolation to the Gauss points, one axis at a time, in place
+        if constexpr (!COLL) {
+            const double *BE = tab + TL.BEO();
+            svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                apply_eo<N, false, false>(BE, x, o);
+                st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+            });
+            __syncthreads();
+            svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                apply_eo<N, false, false>(BE, x, o);
+                st_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+            });
+            __syncthreads();
+            svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                apply_eo<N, false, false>(BE, x, o);
+                st_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+            });
+            __syncthreads();
+        }
+        // reference gradients: axes 1 and 2 into their own tensors, then axis 0 in place
+        const double *DE = tab + TL.DhEO();
+        svk_pencils_12<N, C, NF, NT>(
+            [&](int c, int f, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                apply_eo<N, true, false>(DE, x, o);
+                st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
+            },
+            [&](int c, int f, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                apply_eo<N, true, false>(DE, x, o);
+                st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, o);
+            });
+        __syncthreads();
         svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
             double x[N], o[N];
             ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-            apply_eo<N, false, false>(BE, x, o);
+            apply_eo<N, true, false>(DE, x, o);
             st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
         });
         __syncthreads();
-        svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-            double x[N], o[N];
-            ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-            apply_eo<N, false, false>(BE, x, o);
-            st_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, o);
-        });
-        __syncthreads();
-        svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-            double x[N], o[N];
-            ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-            apply_eo<N, false, false>(BE, x, o);
-            st_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, o);
-        });
-        __syncthreads();
-    }
-    // reference gradients: axes 1 and 2 into their own tensors, then axis 0 in place
-    const double *DE = tab + TL.DhEO();
-    svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-        double x[N], o[N];
-        ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-        apply_eo<N, true, false>(DE, x, o);
-        st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
-    });
-    svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-        double x[N], o[N];
-        ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-        apply_eo<N, true, false>(DE, x, o);
-        st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, o);
-    });
-    __syncthreads();
-    svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-        double x[N], o[N];
-        ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-        apply_eo<N, true, false>(DE, x, o);
-        st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
-    });
-    __syncthreads();
 
-    // pointwise: flux of component c along reference direction d into slot 3c + d
-    {
-        const double *W = tab + TL.W();
-        const double *XQ = tab + TL.XQ();
-        int bad = 0;
-        for (int t = threadIdx.x; t < C * N3; t += NT) {
-            const int c = t / N3;
-            const int i = t - c * N3;
-            const int q0 = i / (N * N), q1 = (i / N) % N, q2 = i % N;
-            const int o = q0 * S1 + q1 * S2 + q2;
-            double gu[3][3], gd[3][3], G[3][3], wdet;
+        // pointwise: flux of component c along reference direction d into slot 3c + d
+        {
+            const double *W = tab + TL.W();
+            const double *XQ = tab + TL.XQ();
+            int bad = 0;
+            for (int t = threadIdx.x; t < C * N3; t += NT) {
+                const int c = t / N3;
+                const int i = t - c * N3;
+                const int q0 = i / (N * N), q1 = (i / N) % N, q2 = i % N;
+                const int o = q0 * S1 + q1 * S2 + q2;
+                double gu[3][3], gd[3][3], G[3][3], wdet;
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    gu[k][d] = tensor(c, 3 * k + d)[o];
-                    if constexpr (JAC) gd[k][d] = tensor(c, 9 + 3 * k + d)[o];
-                    else gd[k][d] = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        gu[k][d] = tensor(c, 3 * k + d)[o];
+                        if constexpr (JAC) gd[k][d] = tensor(c, 9 + 3 * k + d)[o];
+                        else gd[k][d] = 0.0;
+                    }
+                const double w = W[q0] * W[q1] * W[q2];
+                if constexpr (TRI) {
+                    double J[3][3];
+                    const double det = trilinear_jacobian(geo + c * Sh::GEO, XQ[q0], XQ[q1], XQ[q2], J);
+                    if (!(det > 0.0) && cell0 + c < ncells) bad = SF_FLAG_DETJ;
+                    inverse3(J, det, G);
+                    wdet = w * fabs(det);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) G[a][b] = geo[c * Sh::GEO + 24 + 3 * a + b];
+                    wdet = w * geo[c * Sh::GEO + 33];
                 }
-            const double w = W[q0] * W[q1] * W[q2];
-            if constexpr (TRI) {
-                double J[3][3];
-                const double det = trilinear_jacobian(geo + c * Sh::GEO, XQ[q0], XQ[q1], XQ[q2], J);
-                if (!(det > 0.0) && cell0 + c < ncells) bad = SF_FLAG_DETJ;
-                inverse3(J, det, G);
-                wdet = w * fabs(det);
-            } else {
+                svk_point<JAC>(gu, gd, G, wdet, lambda, mu);
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) G[a][b] = geo[c * Sh::GEO + 3 * a + b];
-                wdet = w * geo[c * Sh::GEO + 9];
+                    for (int d = 0; d < 3; ++d) tensor(c, 3 * k + d)[o] = gu[k][d];
             }
-            svk_point<JAC>(gu, gd, G, wdet, lambda, mu);
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) tensor(c, 3 * k + d)[o] = gu[k][d];
+            if (bad) atomicOr(err, bad);
         }
-        if (bad) atomicOr(err, bad);
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // back to the DOFs: Dh^T along axes 1 and 2 in place, then along axis 0 with the
-    // three directions summed (and B^T applied on the same pencil), then B^T along 1, 2
-    const double *DTE = tab + TL.DhTEO();
-    svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-        double x[N], o[N];
-        ld_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
-        apply_eo<N, true, false>(DTE, x, o);
-        st_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
-    });
-    svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-        double x[N], o[N];
-        ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
-        apply_eo<N, true, false>(DTE, x, o);
-        st_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, o);
-    });
-    __syncthreads();
-    const double *BTE = tab + TL.BTEO();
-    svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-        double x[N], o[N];
-        ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-        ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
-        apply_eo<N, true, true>(DTE, x, o);
-        ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+        // back to the DOFs: Dh^T along axes 1 and 2 in place, then along axis 0 with the
+        // three directions summed (and B^T applied on the same pencil), then B^T along 1, 2
+        const double *DTE = tab + TL.DhTEO();
+        svk_pencils_12<N, C, 3, NT>(
+            [&](int c, int k, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
+                apply_eo<N, true, false>(DTE, x, o);
+                st_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+            },
+            [&](int c, int k, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+                apply_eo<N, true, false>(DTE, x, o);
+                st_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, o);
+            });
+        __syncthreads();
+        const double *BTE = tab + TL.BTEO();
+        svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+            ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+            apply_eo<N, true, true>(DTE, x, o);
+            ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
 #pragma unroll
-        for (int j = 0; j < N; ++j) o[j] += x[j];
+            for (int j = 0; j < N; ++j) o[j] += x[j];
+            if constexpr (!COLL) {
+                apply_eo<N, false, false>(BTE, o, x);
+                st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+            } else {
+                st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+            }
+        });
+        __syncthreads();
         if constexpr (!COLL) {
-            apply_eo<N, false, false>(BTE, o, x);
-            st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-        } else {
-            st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+            svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                apply_eo<N, false, false>(BTE, x, o);
+                st_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+            });
+            __syncthreads();
+            svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                apply_eo<N, false, false>(BTE, x, o);
+                st_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+            });
+            __syncthreads();
         }
-    });
-    __syncthreads();
-    if constexpr (!COLL) {
-        svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-            double x[N], o[N];
-            ld_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-            apply_eo<N, false, false>(BTE, x, o);
-            st_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, o);
-        });
-        __syncthreads();
-        svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-            double x[N], o[N];
-            ld_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-            apply_eo<N, false, false>(BTE, x, o);
-            st_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, o);
-        });
-        __syncthreads();
-    }
-    for (int t = threadIdx.x; t < C * 3 * N3; t += NT) {
-        const int c = t / (3 * N3);
-        const int r = t - c * 3 * N3;
-        const int k = r / N3;
-        const int i = r - k * N3;
-        const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
-        if (cell0 + c < ncells) y[(cell0 + c) * (3 * N3) + r] = tensor(c, 3 * k)[i0 * S1 + i1 * S2 + i2];
+        for (int t = threadIdx.x; t < C * 3 * N3; t += NT) {
+            const int c = t / (3 * N3);
+            const int r = t - c * 3 * N3;
+            const int k = r / N3;
+            const int i = r - k * N3;
+            const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
+            if (cell0 + c < ncells) y[(cell0 + c) * (3 * N3) + r] = tensor(c, 3 * k)[i0 * S1 + i1 * S2 + i2];
+        }
+        __syncthreads(); // the next group overwrites the tensors
     }
 }
 
@@ -359,12 +416,22 @@ namespace {
 template <int N, bool COLL, bool JAC, bool TRI> int launch_svk4(const LaunchArgs &a)
 {
     using Sh = SvkShape<N, JAC>;
+    static int resident = 0; // workgroups the device holds at once (occupancy x CUs)
+    auto kern = svk_action_kernel<N, COLL, JAC, TRI>;
+    if (resident <= 0) {
+        int per_cu = 0, ncu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, Sh::NT, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return SF_ERR_HIP;
+        resident = (per_cu > 0 ? per_cu : 1) * (ncu > 0 ? ncu : 1);
+    }
     const int64_t groups = (a.ncells + Sh::C - 1) / Sh::C;
-    if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
+    const int grid = int(groups < resident ? groups : resident);
     const double *f0 = JAC ? static_cast<const double *>(a.kappa) : static_cast<const double *>(a.u);
     const double *f1 = JAC ? static_cast<const double *>(a.u) : nullptr;
-    hipLaunchKernelGGL((svk_action_kernel<N, COLL, JAC, TRI>), dim3(unsigned(groups)), dim3(Sh::NT), 0, a.stream,
-                       a.ncells, a.vert, f0, f1, static_cast<double *>(a.y), a.tab64, a.alpha, a.beta, a.err);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(Sh::NT), 0, a.stream, a.ncells, a.vert, f0, f1,
+                       static_cast<double *>(a.y), a.tab64, a.alpha, a.beta, a.err);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
