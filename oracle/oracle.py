@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sf_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-FAMILIES = {"Q": 0, "DQ": 1, "NCF": 2, "NCE": 3, "QGLL": 4}
+FAMILIES = {"Q": 0, "DQ": 1, "NCF": 2, "NCE": 3, "QGLL": 4, "VQ": 5}
 FORMS = {"MASS": 0, "LAPLACE": 1, "HDIV": 2, "HCURL": 3}
 
 _lib = None

@@ -41,6 +41,9 @@
  *   - H(div) (NCF) blocks: block c is P_k on axis c (GLL_{k+1} nodes) times
  *     dP_{k-1} (GL_k nodes) on the other axes, value +phi e_c;
  *     H(curl) (NCE) blocks: dP_{k-1} on axis c, P_k elsewhere, value +phi e_c;
+ *   - vector Q_p (VQ): three blocks, block c the scalar Q_p element with
+ *     value +phi e_c and no Piola map (Sec. 2.3), i.e. local DOF (c, i) at
+ *     c (p+1)^3 + i;
  *   - contravariant Piola  Psi = J Psi^ / det J,  div Psi = div^ Psi^ / det J;
  *     covariant Piola      Psi = J^{-T} Psi^,    curl Psi = J curl^ Psi^ / det J;
  *   - row i = test function, column j = trial function; y = A u.
@@ -59,6 +62,7 @@
  * nodes and quadrature points coincide (the collocated, under-integrated spectral
  * element variant of Sec. 2.5); the same element as ORC_Q with another rule. */
 #define ORC_QGLL 4
+#define ORC_VQ 5
 #define ORC_NCE 3
 
 #define ORC_MASS 0
@@ -213,6 +217,19 @@ static int make_element(int family, int degree, orc_element *e)
         e->ndof = (degree + 1) * (degree + 1) * (degree + 1);
         return 0;
     }
+    if (family == ORC_VQ) { /* vector Q_p: the scalar basis times the unit vectors (Sec. 2.3) */
+        if (degree < 1 || degree + 1 > ORC_MAXN) return -1;
+        int n = degree + 1;
+        e->nblocks = 3;
+        e->vector = 1;
+        for (int c = 0; c < 3; ++c) {
+            for (int a = 0; a < 3; ++a) set_axis(&e->b[c], a, n, 1);
+            e->b[c].comp = c;
+            e->b[c].offset = c * n * n * n;
+        }
+        e->ndof = 3 * n * n * n;
+        return 0;
+    }
     if (family == ORC_NCF || family == ORC_NCE) {
         int k = degree;
         if (k < 1 || k + 1 > ORC_MAXN) return -1;
@@ -340,10 +357,12 @@ int orc_jacobian(const double *X, const double *xi, double *Jout)
 /*   scalar families: f[i] = (Psi_i, grad Psi_i) with grad = G^T grad^;     */
 /*   NCF:  f[i] = (J Psi^ / det, div^ Psi^ / det);                          */
 /*   NCE:  f[i] = (G^T Psi^, J curl^ Psi^ / det).                           */
-/* 4 slots for scalar / divergence data, 6 for curl data.                   */
+/*   VQ:   f[i] = (Psi^, grad Psi^ G) (no Piola map: the vector element's   */
+/*         values are the scalar basis times fixed unit vectors).           */
+/* 4 slots for scalar / divergence data, 6 for curl data, 12 for VQ.        */
 /* ------------------------------------------------------------------------ */
 
-#define ORC_SLOTS 6
+#define ORC_SLOTS 12
 
 static void push_forward(const orc_element *e, const double *val, const double *grad,
                          double J[3][3], double G[3][3], double det, double *f)
@@ -359,6 +378,15 @@ static void push_forward(const orc_element *e, const double *val, const double *
                 double s = 0.0;
                 for (int b = 0; b < 3; ++b) s += G[b][a] * g[b]; /* (G^T grad^)_a */
                 o[1 + a] = s;
+            }
+        } else if (e->family == ORC_VQ) {
+            for (int c = 0; c < 3; ++c) {
+                o[c] = v[c];
+                for (int a = 0; a < 3; ++a) {
+                    double s = 0.0;
+                    for (int b = 0; b < 3; ++b) s += g[3 * c + b] * G[b][a]; /* d v_c / d x_a */
+                    o[3 + 3 * c + a] = s;
+                }
             }
         } else if (e->family == ORC_NCF) {
             for (int a = 0; a < 3; ++a) {
@@ -395,6 +423,14 @@ static double integrand(int family, int form, double alpha, double beta, const d
         if (form == ORC_MASS) return ft[0] * fs[0];
         return ft[1] * fs[1] + ft[2] * fs[2] + ft[3] * fs[3]; /* LAPLACE */
     }
+    if (family == ORC_VQ) {
+        double m = 0.0;
+        if (form == ORC_MASS)
+            for (int s = 0; s < 3; ++s) m += ft[s] * fs[s]; /* u . v */
+        else
+            for (int s = 3; s < 12; ++s) m += ft[s] * fs[s]; /* grad u : grad v */
+        return m;
+    }
     double m = ft[0] * fs[0] + ft[1] * fs[1] + ft[2] * fs[2];
     if (form == ORC_MASS) return m;
     if (family == ORC_NCF) return alpha * m + beta * ft[3] * fs[3];          /* HDIV  */
@@ -403,7 +439,8 @@ static double integrand(int family, int form, double alpha, double beta, const d
 
 static int form_valid(int family, int form)
 {
-    if (family == ORC_Q || family == ORC_DQ || family == ORC_QGLL) return form == ORC_MASS || form == ORC_LAPLACE;
+    if (family == ORC_Q || family == ORC_DQ || family == ORC_QGLL || family == ORC_VQ)
+        return form == ORC_MASS || form == ORC_LAPLACE;
     if (family == ORC_NCF) return form == ORC_MASS || form == ORC_HDIV;
     if (family == ORC_NCE) return form == ORC_MASS || form == ORC_HCURL;
     return 0;

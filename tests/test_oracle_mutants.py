@@ -33,9 +33,12 @@ MUTANTS = [
      "SVK linearisation: dropped lambda term"),
     ("t += dH[k][a] * F[k][b] + F[k][a] * dH[k][b];", "t += dH[a][k] * F[b][k] + F[a][k] * dH[b][k];",
      "SVK linearisation: transposed dE"),
+    ("for (int b = 0; b < 3; ++b) s += g[3 * c + b] * G[b][a]; /* d v_c / d x_a */",
+     "for (int b = 0; b < 3; ++b) s += g[3 * c + b] * G[a][b];", "vector element: G transposed"),
+    ("e->b[c].offset = c * n * n * n;", "e->b[c].offset = 0;", "vector element: blocks overlap"),
 ]
 PIN_SUITES = [os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_golden.py"),
-              os.path.join(ROOT, "tests", "test_oracle_svk.py")]
+              os.path.join(ROOT, "tests", "test_oracle_svk.py"), os.path.join(ROOT, "tests", "test_oracle_vq.py")]
 
 
 def run_pins_against_copy(tmp_path, old=None, new=None):
