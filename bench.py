@@ -62,10 +62,11 @@ def main():
                          "every degree now; 'off' keeps the library defaults")
     ap.add_argument("--no-tune", dest="tune", action="store_const", const="off", help="same as --tune off")
     ap.add_argument("--save-tuning", default="", help="write the tuning choices used to this JSON file")
-    ap.add_argument("--legs", default="mass,collocated,trilinear,svk,global,vec,matrix,batch",
+    ap.add_argument("--legs", default="mass,collocated,trilinear,vq,svk,global,vec,matrix,batch",
                     help="side measurements beside the headline: mass (Q_p mass action, 64^3), collocated "
                          "(Laplace action with the GLL rule, B = I, 64^3), trilinear (Laplace action on general "
-                         "trilinear cells, per-point geometry, 64^3 cells), svk (Saint Venant-Kirchhoff "
+                         "trilinear cells, per-point geometry, 64^3 cells), vq (vector Q_p Laplace action, 64^3, and "
+                         "its block-diagonal element matrices), svk (Saint Venant-Kirchhoff "
                          "linearised residual on vector Q_p, 64^3 cells), global (the "
                          "assembled C0 Q_p Laplace action on global vectors, 64^3), vec (NCF/NCE "
                          "actions, 48^3), matrix (Q_p Laplace element matrices), batch (2048-mesh batched "
@@ -183,6 +184,8 @@ def main():
                                                   family="QGLL", form="LAPLACE")
     if "trilinear" in legs:
         side["trilinear_laplace"] = trilinear_leg(sf, V.shape[0], degrees, bufs, args.steps, stream)
+    if "vq" in legs:
+        side["vector_q"] = vq_leg(sf, ctx, V, degrees, args.steps, stream)
     if "svk" in legs:
         side["svk_hyperelastic"] = svk_leg(sf, ctx, V, degrees, args.steps, stream)
     if "global" in legs:
@@ -330,6 +333,44 @@ def trilinear_leg(sf, ncells, degrees, bufs, reps, stream):
     assert sf.sf_check_errors(c) == 0
     c.close()
     return out
+
+
+def vq_leg(sf, ctx, V, degrees, reps, stream):
+    """Vector Q_p element (3 (p+1)^3 DOFs per cell): the vector Laplace action on the 64^3 box
+    mesh (kappa per point U[0.5, 2], u N(0, 1), drawn on the GPU; algorithmic bytes per cell
+    8 (6 n^3 + n^3) + 192), and its block-diagonal element matrices on the first 4096 cells
+    (p = 1..4; bytes written 8 (3 n^3)^2 per cell, of which the off-diagonal two thirds are the
+    cleared buffer)."""
+    import torch
+
+    from paper_1711_02473_amd import synth
+
+    ncells = V.shape[0]
+    act, mat = {}, {}
+    for p in degrees:
+        n3 = (p + 1) ** 3
+        op = sf.make_op("VQ", p, "LAPLACE")
+        kap = synth.device_kappa(ncells, n3, 3, p)
+        _, u = synth.device_displacements(ncells, 3 * n3, 3, p)
+        y = torch.empty_like(u)
+        sf.assemble_action(ctx, op, ncells, V, kap, u, y, stream)
+        ms = timed(lambda it: sf.assemble_action(ctx, op, ncells, V, kap, u, y, stream), reps, stream)
+        gbs = ncells * (8 * 7 * n3 + 192) / (ms / 1e3) / 1e9
+        act[str(p)] = {"ms": round(ms, 4), "gdofs_local": round(ncells * 3 * n3 / (ms / 1e3) / 1e9, 3),
+                       "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+        del kap, u, y
+        if p <= 4:
+            nm = 4096
+            A = torch.empty((nm, 3 * n3, 3 * n3), dtype=torch.float64, device="cuda")
+            kap = synth.device_kappa(nm, n3, 3, p)
+            sf.assemble_element_matrix(ctx, op, nm, V[:nm], kap, A, stream)
+            ms = timed(lambda it: sf.assemble_element_matrix(ctx, op, nm, V[:nm], kap, A, stream), reps, stream)
+            gbs = nm * 8 * (3 * n3) ** 2 / (ms / 1e3) / 1e9
+            mat[str(p)] = {"ms": round(ms, 4), "cells": nm, "hbm_gbs": round(gbs, 1),
+                           "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+            del A, kap
+    assert sf.sf_check_errors(ctx) == 0
+    return {"laplace_action": act, "laplace_element_matrix": mat}
 
 
 def svk_leg(sf, ctx, V, degrees, reps, stream, lam=1.3, mu=0.8):

@@ -77,7 +77,16 @@ extern "C" {
  * and nodes coincide (B = I): the collocated, under-integrated spectral-element
  * variant (Sec. 2.5).  Its mass matrix is diagonal (lumped); the 1-D stiffness
  * is still integrated exactly.  kappa is given at the GLL points. */
-enum { SF_Q = 0, SF_DQ = 1, SF_NCF = 2, SF_NCE = 3, SF_QGLL = 4 };
+/* SF_VQ: the vector Q_p element, the scalar SF_Q basis times the three unit
+ * vectors (Sec. 2.3): ndof_cell = 3 (p+1)^3, local DOF (component c, node i)
+ * at c (p+1)^3 + i (three component blocks), p = 1..8, the (p+1)-point GL
+ * rule, kappa scalar per point.  Forms SF_MASS (kappa u . v) and SF_LAPLACE
+ * (kappa grad u : grad v); FP64 contractions and SF_F64 storage only.  Its
+ * element matrices are block diagonal, the SF_Q matrix in each diagonal
+ * block: computed once per cell and assigned to the three diagonal views of
+ * the output after the whole output has been cleared (delta cancellation
+ * across the assignment, Sec. 3.4); box cells, as for SF_Q. */
+enum { SF_Q = 0, SF_DQ = 1, SF_NCF = 2, SF_NCE = 3, SF_QGLL = 4, SF_VQ = 5 };
 enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3, SF_SVK = 4, SF_SVK_RESIDUAL = 5 };
 /* SF_SVK / SF_SVK_RESIDUAL: the Saint Venant-Kirchhoff hyperelastic model of
  * the paper's evaluation on the VECTOR Q_p element (family SF_Q, or SF_QGLL
@@ -112,7 +121,7 @@ typedef struct sf_context sf_context;
 typedef struct sf_batch sf_batch;
 
 typedef struct {
-    int32_t family;    /* SF_Q, SF_DQ, SF_QGLL: degree p in 1..8;  SF_NCF, SF_NCE: k in 1..6 */
+    int32_t family;    /* SF_Q, SF_DQ, SF_QGLL, SF_VQ: degree p in 1..8;  SF_NCF, SF_NCE: k in 1..6 */
     int32_t degree;
     int32_t form;      /* see above                                                 */
     int32_t nq1;       /* GL points per axis; 0 => degree + 1 (see sf_element_dims) */
@@ -239,7 +248,7 @@ int64_t sf_concat_index(int32_t ndim, int32_t nblocks, const int32_t *extents, i
 
 /* Host only.  Per-block extents of the element of `op` (family and degree):
  * *nblocks in {1,3}; extents[b*3+a] functions of block b along axis a;
- * offsets[b] the block's first local index (the vector element of SF_SVK:
+ * offsets[b] the block's first local index (the vector element of SF_VQ and SF_SVK:
  * three blocks of (p+1)^3, one per component). */
 int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t *offsets);
 

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsf.so")
 
-FAMILY = {"Q": 0, "DQ": 1, "NCF": 2, "NCE": 3, "QGLL": 4}
+FAMILY = {"Q": 0, "DQ": 1, "NCF": 2, "NCE": 3, "QGLL": 4, "VQ": 5}
 FORM = {"MASS": 0, "LAPLACE": 1, "HDIV": 2, "HCURL": 3, "SVK": 4, "SVK_RESIDUAL": 5}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 IO = {"f64": 0, "f32": 1}

@@ -20,13 +20,14 @@ struct Dims {
 };
 
 bool scalar_family(int family) { return family == SF_Q || family == SF_DQ || family == SF_QGLL; }
-int degree_max(int family) { return scalar_family(family) ? 8 : 6; }
+int degree_max(int family) { return (scalar_family(family) || family == SF_VQ) ? 8 : 6; }
 
 bool svk_form(int form) { return form == SF_SVK || form == SF_SVK_RESIDUAL; }
 
 bool form_ok(int family, int form)
 {
     if (svk_form(form)) return family == SF_Q || family == SF_QGLL;
+    if (family == SF_VQ) return form == SF_MASS || form == SF_LAPLACE;
     if (scalar_family(family)) return form == SF_MASS || form == SF_LAPLACE;
     if (family == SF_NCF) return form == SF_MASS || form == SF_HDIV;
     if (family == SF_NCE) return form == SF_MASS || form == SF_HCURL;
@@ -37,7 +38,7 @@ bool form_ok(int family, int form)
 int check_op(const sf_op *op, Dims *d)
 {
     if (!op) return SF_ERR_ARG;
-    if (op->family < SF_Q || op->family > SF_QGLL) return SF_ERR_UNSUPPORTED;
+    if (op->family < SF_Q || op->family > SF_VQ) return SF_ERR_UNSUPPORTED;
     if (op->degree < 1 || op->degree > degree_max(op->family)) return SF_ERR_UNSUPPORTED;
     if (!form_ok(op->family, op->form)) return SF_ERR_UNSUPPORTED;
     if (op->nq1 < 0) return SF_ERR_ARG;
@@ -47,14 +48,15 @@ int check_op(const sf_op *op, Dims *d)
     const int p = op->degree;
     const int nq1 = op->nq1 ? op->nq1 : p + 1;
     if (nq1 != p + 1) return SF_ERR_UNSUPPORTED; // kernels are built for p+1 Gauss points per axis
-    if (svk_form(op->form) && (op->precision != SF_FP64 || op->io_dtype != SF_F64)) return SF_ERR_UNSUPPORTED;
+    if ((svk_form(op->form) || op->family == SF_VQ) && (op->precision != SF_FP64 || op->io_dtype != SF_F64))
+        return SF_ERR_UNSUPPORTED;
     Dims r;
     r.nq1 = nq1;
     r.nq = nq1 * nq1 * nq1;
-    if (scalar_family(op->family)) {
+    if (scalar_family(op->family) || op->family == SF_VQ) {
         r.n0 = p + 1;
         r.n1 = 0;
-        r.ndof = (svk_form(op->form) ? 3 : 1) * (p + 1) * (p + 1) * (p + 1);
+        r.ndof = ((svk_form(op->form) || op->family == SF_VQ) ? 3 : 1) * (p + 1) * (p + 1) * (p + 1);
     } else {
         r.n0 = p + 1; // P_k factor
         r.n1 = p;     // dP_{k-1} factor
@@ -374,10 +376,10 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     if (rc) return rc;
     a.u = u;
     a.y = y;
-    if (svk_form(op->form)) {
+    if (svk_form(op->form) || op->family == SF_VQ) {
         if (op->form == SF_SVK_RESIDUAL && kappa) return SF_ERR_ARG;
         a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
-        return launch_action_svk(a);
+        return launch_action_vq(a);
     }
     if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
         return launch_action_mixed(a);
@@ -435,7 +437,7 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
     rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
     if (rc) return rc;
     a.A = A;
-    if (scalar_family(op->family)) return launch_matrix_q(a);
+    if (scalar_family(op->family) || op->family == SF_VQ) return launch_matrix_q(a);
     return launch_matrix_vec(a);
 }
 
@@ -489,7 +491,7 @@ int sf_block_layout(const sf_op *op, int32_t *nblocks, int32_t *extents, int32_t
     if (rc) return rc;
     if (!nblocks || !extents || !offsets) return SF_ERR_ARG;
     const int p = op->degree;
-    if (svk_form(op->form)) { // vector element: one scalar block per component
+    if (svk_form(op->form) || op->family == SF_VQ) { // vector element: one scalar block per component
         *nblocks = 3;
         for (int c = 0; c < 3; ++c) {
             extents[c * 3] = extents[c * 3 + 1] = extents[c * 3 + 2] = p + 1;

@@ -27,18 +27,26 @@
 
 namespace sf {
 
-template <int N, int NQ, int FORM, typename IO, int C, int NT>
+template <int N, int NQ, int FORM, typename IO, int C, int NT, int R>
 __global__ void __launch_bounds__(NT) matrix_q_kernel(const int64_t ncells, const double *__restrict__ vert,
                                                       const IO *__restrict__ kappa, IO *__restrict__ A,
                                                       const double *__restrict__ tab, int *__restrict__ err)
 {
     __shared__ double smem[MatrixQSmem<N, NQ, FORM, C>::doubles];
-    matrix_q_body<N, NQ, FORM, IO, C, NT>(int64_t(blockIdx.x) * C, ncells, vert, kappa, A, 0, tab, err, smem);
+    matrix_q_body<N, NQ, FORM, IO, C, NT, R>(int64_t(blockIdx.x) * C, ncells, vert, kappa, A, 0, tab, err, smem);
+}
+
+// clears the off-diagonal blocks' buffer before the vector element's diagonal
+// blocks are assigned (a kernel, not a memset, so that the launch can be captured)
+template <typename IO> __global__ void matrix_clear_kernel(IO *A, int64_t n)
+{
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+        A[t] = IO(0);
 }
 
 namespace {
 
-template <int N, int FORM, typename IO>
+template <int N, int FORM, typename IO, int R>
 int launch_one(const LaunchArgs &a)
 {
     constexpr int N3 = N * N * N;
@@ -47,19 +55,32 @@ int launch_one(const LaunchArgs &a)
     constexpr int NT = NT0 > 1024 ? 1024 : NT0;
     const int64_t groups = (a.ncells + C - 1) / C;
     if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
-    hipLaunchKernelGGL((matrix_q_kernel<N, N, FORM, IO, C, NT>), dim3(unsigned(groups)), dim3(NT), 0, a.stream,
+    if (R > 1) {
+        const int64_t n = a.ncells * int64_t(R * N3) * (R * N3);
+        const int64_t blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+        hipLaunchKernelGGL(matrix_clear_kernel<IO>, dim3(unsigned(blocks)), dim3(256), 0, a.stream,
+                           static_cast<IO *>(a.A), n);
+    }
+    hipLaunchKernelGGL((matrix_q_kernel<N, N, FORM, IO, C, NT, R>), dim3(unsigned(groups)), dim3(NT), 0, a.stream,
                        a.ncells, a.vert, static_cast<const IO *>(a.kappa), static_cast<IO *>(a.A), a.tab64, a.err);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+template <int N, int R>
+int launch_nr(const LaunchArgs &a)
+{
+    if (a.precision != SF_FP64) return SF_ERR_UNSUPPORTED;
+    if (a.form == SF_MASS)
+        return a.io == SF_F64 ? launch_one<N, SF_MASS, double, R>(a) : launch_one<N, SF_MASS, float, R>(a);
+    if (a.form == SF_LAPLACE)
+        return a.io == SF_F64 ? launch_one<N, SF_LAPLACE, double, R>(a) : launch_one<N, SF_LAPLACE, float, R>(a);
+    return SF_ERR_UNSUPPORTED;
 }
 
 template <int N>
 int launch_n(const LaunchArgs &a)
 {
-    if (a.precision != SF_FP64) return SF_ERR_UNSUPPORTED;
-    if (a.form == SF_MASS) return a.io == SF_F64 ? launch_one<N, SF_MASS, double>(a) : launch_one<N, SF_MASS, float>(a);
-    if (a.form == SF_LAPLACE)
-        return a.io == SF_F64 ? launch_one<N, SF_LAPLACE, double>(a) : launch_one<N, SF_LAPLACE, float>(a);
-    return SF_ERR_UNSUPPORTED;
+    return a.family == SF_VQ ? launch_nr<N, 3>(a) : launch_nr<N, 1>(a);
 }
 
 } // namespace

@@ -1,6 +1,7 @@
-// Saint Venant-Kirchhoff hyperelasticity on the vector Q_p element (the
-// hyperelastic model of the paper's evaluation; vector element of Sec. 2.3),
-// matrix-free, FP64, on gfx950.
+// Actions on the vector Q_p element (vector element of Sec. 2.3), matrix-free,
+// FP64, on gfx950: the vector mass and vector Laplace forms (family SF_VQ,
+// pointwise coefficient kappa) and Saint Venant-Kirchhoff hyperelasticity (the
+// hyperelastic model of the paper's evaluation: forms SF_SVK, SF_SVK_RESIDUAL).
 //
 // Vector element: the scalar Q_p basis (GLL nodes) times the unit vectors,
 // local DOF (component c, node i) at c * n^3 + i.  Because every vector
@@ -10,6 +11,7 @@
 // backward contraction chain per component (delta cancellation, Sec. 3.4).
 //
 // Per point, with grad u = (reference gradient) G, G = J^{-1}:
+//   vector mass:     w kappa |det J| u;   vector Laplace: w kappa |det J| grad u G^T;
 //   F = I + grad u,  E = (F^T F - I) / 2,  S = lambda tr(E) I + 2 mu E,
 //   residual form:   P = F S
 //   linearised form: dF = grad du, dE = (dF^T F + F^T dF) / 2,
@@ -37,21 +39,22 @@ namespace sf {
 
 // threads per workgroup: 512 where one cell's eighteen tensors fill most of
 // the LDS (one workgroup per CU), so that the CU still holds eight waves
-__host__ __device__ constexpr int svk_nt(int n, bool jac) { return (jac && n >= 8) ? 512 : 256; }
+__host__ __device__ constexpr int vq_nt(int n, int form) { return (form == SF_SVK && n >= 8) ? 512 : 256; }
 
-template <int N, bool JAC> struct SvkShape {
+template <int N, int FORM> struct VqShape {
     using L = Lds3<N>;
-    static constexpr int NF = JAC ? 6 : 3; // interpolated fields
-    static constexpr int NS = 3 * NF;      // LDS tensors per cell
-    static constexpr int GEO = 34;         // per-cell geometry: vertices (24), G (9), |det J|
+    static constexpr int NF = FORM == SF_SVK ? 6 : 3;   // interpolated fields
+    static constexpr int SPF = FORM == SF_MASS ? 1 : 3; // LDS tensors per field
+    static constexpr int NS = SPF * NF;                 // LDS tensors per cell
+    static constexpr int GEO = 34;                      // per-cell geometry: vertices (24), G (9), |det J|
     static constexpr int CELL = NS * L::CS + GEO;
     static constexpr int C = (8192 / CELL) > 0 ? 8192 / CELL : 1; // about 64 KB of tensors per group
-    static constexpr int NT = svk_nt(N, JAC);
+    static constexpr int NT = vq_nt(N, FORM);
 };
 
 // Loop over the C * NF * N * N pencils along one axis of field tensors
 // (slot 3 f + SLOT of every cell): f(cell, field, a, b).
-template <int N, int C, int NF, int NT, typename Fn> __device__ __forceinline__ void svk_pencils(Fn &&fn)
+template <int N, int C, int NF, int NT, typename Fn> __device__ __forceinline__ void vq_pencils(Fn &&fn)
 {
     constexpr int NP = N * N, PER = NF * NP;
     for (int t = threadIdx.x; t < C * PER; t += NT) {
@@ -67,7 +70,7 @@ template <int N, int C, int NF, int NT, typename Fn> __device__ __forceinline__ 
 // Two independent pencil stages over the same fields, one along axis 1 (f1) and
 // one along axis 2 (f2), run as one loop so that all threads have work.
 template <int N, int C, int NF, int NT, typename F1, typename F2>
-__device__ __forceinline__ void svk_pencils_12(F1 &&f1, F2 &&f2)
+__device__ __forceinline__ void vq_pencils_12(F1 &&f1, F2 &&f2)
 {
     constexpr int NP = N * N, PER = NF * NP, TOT = C * PER;
     for (int t = threadIdx.x; t < 2 * TOT; t += NT) {
@@ -167,22 +170,36 @@ __device__ __forceinline__ void svk_point(double (&gu)[3][3], const double (&gd)
         for (int d = 0; d < 3; ++d) gu[c][d] = wdet * (P[c][0] * G[d][0] + P[c][1] * G[d][1] + P[c][2] * G[d][2]);
 }
 
-template <int N, bool COLL, bool JAC, bool TRI>
-__global__ void __launch_bounds__(svk_nt(N, JAC))
-    svk_action_kernel(const int64_t ncells, const double *__restrict__ vert, const double *__restrict__ f0,
-                      const double *__restrict__ f1, double *__restrict__ y, const double *__restrict__ tab,
-                      const double lambda, const double mu, int *__restrict__ err)
+// Vector Laplace pointwise stage: reference gradients gu -> w kappa |det J| (gu G) G^T.
+__device__ __forceinline__ void vlap_point(double (&gu)[3][3], const double (&G)[3][3], double s)
 {
-    using Sh = SvkShape<N, JAC>;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double h[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) h[e] = gu[c][0] * G[0][e] + gu[c][1] * G[1][e] + gu[c][2] * G[2][e];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gu[c][d] = s * (h[0] * G[d][0] + h[1] * G[d][1] + h[2] * G[d][2]);
+    }
+}
+
+template <int N, bool COLL, int FORM, bool TRI>
+__global__ void __launch_bounds__(vq_nt(N, FORM))
+    vq_action_kernel(const int64_t ncells, const double *__restrict__ vert, const double *__restrict__ f0,
+                     const double *__restrict__ f1, const double *__restrict__ coef, double *__restrict__ y,
+                     const double *__restrict__ tab, const double lambda, const double mu, int *__restrict__ err)
+{
+    using Sh = VqShape<N, FORM>;
     using L = Lds3<N>;
-    constexpr int C = Sh::C, NF = Sh::NF, NS = Sh::NS, NT = Sh::NT, N3 = N * N * N;
+    constexpr bool JAC = FORM == SF_SVK, GRAD = FORM != SF_MASS;
+    constexpr int C = Sh::C, NF = Sh::NF, NS = Sh::NS, SPF = Sh::SPF, NT = Sh::NT, N3 = N * N * N;
     constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
     constexpr TabLayout TL(N, 0, N);
     // inputs of one group: C * NF * N3 field values, then C * 24 vertex coordinates
     constexpr int NFLD = C * NF * N3, NIN = NFLD + C * 24, K = (NIN + NT - 1) / NT;
     __shared__ double smem[C * Sh::CELL];
     double *geo = smem;              // [C][GEO]: vertices (24), G (9), |det J|
-    double *ts = smem + C * Sh::GEO; // [C][NS][CS], field f: slots 3f (values / d0), 3f+1 (d1), 3f+2 (d2)
+    double *ts = smem + C * Sh::GEO; // [C][NS][CS], field f: slots SPF f (values / d0), SPF f + 1 (d1), + 2 (d2)
     auto tensor = [&](int c, int s) { return ts + (c * NS + s) * CS; };
     const int64_t ngroups = (ncells + C - 1) / C;
 
@@ -226,7 +243,7 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
                 const int f = r / N3;
                 const int i = r - f * N3;
                 const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
-                tensor(c, 3 * f)[i0 * S1 + i1 * S2 + i2] = pf[k];
+                tensor(c, SPF * f)[i0 * S1 + i1 * S2 + i2] = pf[k];
             } else if (t < NIN) {
                 const int c = (t - NFLD) / 24;
                 geo[c * Sh::GEO + (t - NFLD - c * 24)] = pf[k];
@@ -260,53 +277,56 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
         // interpolation to the Gauss points, one axis at a time, in place
         if constexpr (!COLL) {
             const double *BE = tab + TL.BEO();
-            svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                ld_pencil<0, N, S1, S2>(tensor(c, SPF * f), a, b, x);
                 apply_eo<N, false, false>(BE, x, o);
-                st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+                st_pencil<0, N, S1, S2>(tensor(c, SPF * f), a, b, o);
             });
             __syncthreads();
-            svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                ld_pencil<1, N, S1, S2>(tensor(c, SPF * f), a, b, x);
                 apply_eo<N, false, false>(BE, x, o);
-                st_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+                st_pencil<1, N, S1, S2>(tensor(c, SPF * f), a, b, o);
             });
             __syncthreads();
-            svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                ld_pencil<2, N, S1, S2>(tensor(c, SPF * f), a, b, x);
                 apply_eo<N, false, false>(BE, x, o);
-                st_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, o);
+                st_pencil<2, N, S1, S2>(tensor(c, SPF * f), a, b, o);
             });
             __syncthreads();
         }
         // reference gradients: axes 1 and 2 into their own tensors, then axis 0 in place
-        const double *DE = tab + TL.DhEO();
-        svk_pencils_12<N, C, NF, NT>(
-            [&](int c, int f, int a, int b) {
+        if constexpr (GRAD) {
+            const double *DE = tab + TL.DhEO();
+            vq_pencils_12<N, C, NF, NT>(
+                [&](int c, int f, int a, int b) {
+                    double x[N], o[N];
+                    ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                    apply_eo<N, true, false>(DE, x, o);
+                    st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
+                },
+                [&](int c, int f, int a, int b) {
+                    double x[N], o[N];
+                    ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                    apply_eo<N, true, false>(DE, x, o);
+                    st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, o);
+                });
+            __syncthreads();
+            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
                 apply_eo<N, true, false>(DE, x, o);
-                st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
-            },
-            [&](int c, int f, int a, int b) {
-                double x[N], o[N];
-                ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-                apply_eo<N, true, false>(DE, x, o);
-                st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, o);
+                st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
             });
-        __syncthreads();
-        svk_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-            double x[N], o[N];
-            ld_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-            apply_eo<N, true, false>(DE, x, o);
-            st_pencil<0, N, S1, S2>(tensor(c, 3 * f), a, b, o);
-        });
-        __syncthreads();
+            __syncthreads();
+        }
 
         // pointwise: flux of component c along reference direction d into slot 3c + d
+        // (mass: the scaled value of component c in slot c)
         {
             const double *W = tab + TL.W();
             const double *XQ = tab + TL.XQ();
@@ -316,15 +336,7 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
                 const int i = t - c * N3;
                 const int q0 = i / (N * N), q1 = (i / N) % N, q2 = i % N;
                 const int o = q0 * S1 + q1 * S2 + q2;
-                double gu[3][3], gd[3][3], G[3][3], wdet;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        gu[k][d] = tensor(c, 3 * k + d)[o];
-                        if constexpr (JAC) gd[k][d] = tensor(c, 9 + 3 * k + d)[o];
-                        else gd[k][d] = 0.0;
-                    }
+                double G[3][3], wdet;
                 const double w = W[q0] * W[q1] * W[q2];
                 if constexpr (TRI) {
                     double J[3][3];
@@ -339,11 +351,29 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
                         for (int b = 0; b < 3; ++b) G[a][b] = geo[c * Sh::GEO + 24 + 3 * a + b];
                     wdet = w * geo[c * Sh::GEO + 33];
                 }
-                svk_point<JAC>(gu, gd, G, wdet, lambda, mu);
+                if constexpr (FORM == SF_MASS || FORM == SF_LAPLACE) {
+                    if (coef != nullptr && cell0 + c < ncells) wdet *= coef[(cell0 + c) * N3 + i];
+                }
+                if constexpr (FORM == SF_MASS) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
+                    for (int k = 0; k < 3; ++k) tensor(c, k)[o] *= wdet;
+                } else {
+                    double gu[3][3], gd[3][3];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) tensor(c, 3 * k + d)[o] = gu[k][d];
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            gu[k][d] = tensor(c, 3 * k + d)[o];
+                            if constexpr (JAC) gd[k][d] = tensor(c, 9 + 3 * k + d)[o];
+                            else gd[k][d] = 0.0;
+                        }
+                    if constexpr (FORM == SF_LAPLACE) vlap_point(gu, G, wdet);
+                    else svk_point<JAC>(gu, gd, G, wdet, lambda, mu);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) tensor(c, 3 * k + d)[o] = gu[k][d];
+                }
             }
             if (bad) atomicOr(err, bad);
         }
@@ -351,51 +381,61 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
 
         // back to the DOFs: Dh^T along axes 1 and 2 in place, then along axis 0 with the
         // three directions summed (and B^T applied on the same pencil), then B^T along 1, 2
-        const double *DTE = tab + TL.DhTEO();
-        svk_pencils_12<N, C, 3, NT>(
-            [&](int c, int k, int a, int b) {
-                double x[N], o[N];
-                ld_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
-                apply_eo<N, true, false>(DTE, x, o);
-                st_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
-            },
-            [&](int c, int k, int a, int b) {
-                double x[N], o[N];
-                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
-                apply_eo<N, true, false>(DTE, x, o);
-                st_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, o);
-            });
-        __syncthreads();
         const double *BTE = tab + TL.BTEO();
-        svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-            double x[N], o[N];
-            ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-            ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
-            apply_eo<N, true, true>(DTE, x, o);
-            ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
-#pragma unroll
-            for (int j = 0; j < N; ++j) o[j] += x[j];
-            if constexpr (!COLL) {
-                apply_eo<N, false, false>(BTE, o, x);
-                st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-            } else {
-                st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
-            }
-        });
-        __syncthreads();
-        if constexpr (!COLL) {
-            svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+        if constexpr (GRAD) {
+            const double *DTE = tab + TL.DhTEO();
+            vq_pencils_12<N, C, 3, NT>(
+                [&](int c, int k, int a, int b) {
+                    double x[N], o[N];
+                    ld_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
+                    apply_eo<N, true, false>(DTE, x, o);
+                    st_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+                },
+                [&](int c, int k, int a, int b) {
+                    double x[N], o[N];
+                    ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+                    apply_eo<N, true, false>(DTE, x, o);
+                    st_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, o);
+                });
+            __syncthreads();
+            vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-                apply_eo<N, false, false>(BTE, x, o);
-                st_pencil<1, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+                ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+                apply_eo<N, true, true>(DTE, x, o);
+                ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+#pragma unroll
+                for (int j = 0; j < N; ++j) o[j] += x[j];
+                if constexpr (!COLL) {
+                    apply_eo<N, false, false>(BTE, o, x);
+                    st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                } else {
+                    st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+                }
             });
             __syncthreads();
-            svk_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+        } else if constexpr (!COLL) {
+            vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                ld_pencil<0, N, S1, S2>(tensor(c, SPF * k), a, b, x);
                 apply_eo<N, false, false>(BTE, x, o);
-                st_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+                st_pencil<0, N, S1, S2>(tensor(c, SPF * k), a, b, o);
+            });
+            __syncthreads();
+        }
+        if constexpr (!COLL) {
+            vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<1, N, S1, S2>(tensor(c, SPF * k), a, b, x);
+                apply_eo<N, false, false>(BTE, x, o);
+                st_pencil<1, N, S1, S2>(tensor(c, SPF * k), a, b, o);
+            });
+            __syncthreads();
+            vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<2, N, S1, S2>(tensor(c, SPF * k), a, b, x);
+                apply_eo<N, false, false>(BTE, x, o);
+                st_pencil<2, N, S1, S2>(tensor(c, SPF * k), a, b, o);
             });
             __syncthreads();
         }
@@ -405,7 +445,7 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
             const int k = r / N3;
             const int i = r - k * N3;
             const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
-            if (cell0 + c < ncells) y[(cell0 + c) * (3 * N3) + r] = tensor(c, 3 * k)[i0 * S1 + i1 * S2 + i2];
+            if (cell0 + c < ncells) y[(cell0 + c) * (3 * N3) + r] = tensor(c, SPF * k)[i0 * S1 + i1 * S2 + i2];
         }
         __syncthreads(); // the next group overwrites the tensors
     }
@@ -413,11 +453,11 @@ __global__ void __launch_bounds__(svk_nt(N, JAC))
 
 namespace {
 
-template <int N, bool COLL, bool JAC, bool TRI> int launch_svk4(const LaunchArgs &a)
+template <int N, bool COLL, int FORM, bool TRI> int launch_vq4(const LaunchArgs &a)
 {
-    using Sh = SvkShape<N, JAC>;
+    using Sh = VqShape<N, FORM>;
     static int resident = 0; // workgroups the device holds at once (occupancy x CUs)
-    auto kern = svk_action_kernel<N, COLL, JAC, TRI>;
+    auto kern = vq_action_kernel<N, COLL, FORM, TRI>;
     if (resident <= 0) {
         int per_cu = 0, ncu = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -428,40 +468,50 @@ template <int N, bool COLL, bool JAC, bool TRI> int launch_svk4(const LaunchArgs
     }
     const int64_t groups = (a.ncells + Sh::C - 1) / Sh::C;
     const int grid = int(groups < resident ? groups : resident);
-    const double *f0 = JAC ? static_cast<const double *>(a.kappa) : static_cast<const double *>(a.u);
-    const double *f1 = JAC ? static_cast<const double *>(a.u) : nullptr;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(Sh::NT), 0, a.stream, a.ncells, a.vert, f0, f1,
+    // SF_SVK: fields u0 (the coefficient) and du; the others: the input vector, with
+    // kappa as the pointwise coefficient of the vector mass / Laplace forms
+    const double *f0 = FORM == SF_SVK ? static_cast<const double *>(a.kappa) : static_cast<const double *>(a.u);
+    const double *f1 = FORM == SF_SVK ? static_cast<const double *>(a.u) : nullptr;
+    const double *coef = (FORM == SF_MASS || FORM == SF_LAPLACE) ? static_cast<const double *>(a.kappa) : nullptr;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(Sh::NT), 0, a.stream, a.ncells, a.vert, f0, f1, coef,
                        static_cast<double *>(a.y), a.tab64, a.alpha, a.beta, a.err);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
-template <int N> int launch_svk_n(const LaunchArgs &a)
+template <int N, int FORM> int launch_vq_geo(const LaunchArgs &a)
 {
-    const bool coll = a.family == SF_QGLL;
-    const bool jac = a.form == SF_SVK;
-    if (coll) {
-        if (jac) return a.trilinear ? launch_svk4<N, true, true, true>(a) : launch_svk4<N, true, true, false>(a);
-        return a.trilinear ? launch_svk4<N, true, false, true>(a) : launch_svk4<N, true, false, false>(a);
+    if (a.family == SF_QGLL) return a.trilinear ? launch_vq4<N, true, FORM, true>(a) : launch_vq4<N, true, FORM, false>(a);
+    return a.trilinear ? launch_vq4<N, false, FORM, true>(a) : launch_vq4<N, false, FORM, false>(a);
+}
+
+template <int N> int launch_vq_n(const LaunchArgs &a)
+{
+    switch (a.form) {
+    case SF_SVK: return launch_vq_geo<N, SF_SVK>(a);
+    case SF_SVK_RESIDUAL: return launch_vq_geo<N, SF_SVK_RESIDUAL>(a);
+    case SF_MASS: return a.trilinear ? launch_vq4<N, false, SF_MASS, true>(a) : launch_vq4<N, false, SF_MASS, false>(a);
+    case SF_LAPLACE:
+        return a.trilinear ? launch_vq4<N, false, SF_LAPLACE, true>(a) : launch_vq4<N, false, SF_LAPLACE, false>(a);
+    default: return SF_ERR_UNSUPPORTED;
     }
-    if (jac) return a.trilinear ? launch_svk4<N, false, true, true>(a) : launch_svk4<N, false, true, false>(a);
-    return a.trilinear ? launch_svk4<N, false, false, true>(a) : launch_svk4<N, false, false, false>(a);
 }
 
 } // namespace
 
-int launch_action_svk(const LaunchArgs &a)
+int launch_action_vq(const LaunchArgs &a)
 {
     if (a.nq != a.degree + 1 || a.precision != SF_FP64 || a.io != SF_F64) return SF_ERR_UNSUPPORTED;
-    if (a.family != SF_Q && a.family != SF_QGLL) return SF_ERR_UNSUPPORTED;
+    const bool svk = a.form == SF_SVK || a.form == SF_SVK_RESIDUAL;
+    if (svk ? (a.family != SF_Q && a.family != SF_QGLL) : (a.family != SF_VQ)) return SF_ERR_UNSUPPORTED;
     switch (a.degree + 1) {
-    case 2: return launch_svk_n<2>(a);
-    case 3: return launch_svk_n<3>(a);
-    case 4: return launch_svk_n<4>(a);
-    case 5: return launch_svk_n<5>(a);
-    case 6: return launch_svk_n<6>(a);
-    case 7: return launch_svk_n<7>(a);
-    case 8: return launch_svk_n<8>(a);
-    case 9: return launch_svk_n<9>(a);
+    case 2: return launch_vq_n<2>(a);
+    case 3: return launch_vq_n<3>(a);
+    case 4: return launch_vq_n<4>(a);
+    case 5: return launch_vq_n<5>(a);
+    case 6: return launch_vq_n<6>(a);
+    case 7: return launch_vq_n<7>(a);
+    case 8: return launch_vq_n<8>(a);
+    case 9: return launch_vq_n<9>(a);
     default: return SF_ERR_UNSUPPORTED;
     }
 }

@@ -151,3 +151,17 @@ def test_svk_vector_element_dims_layout_and_validation():
                 sf.make_op("Q", 2, "SVK", io="f32"), sf.make_op("Q", 9, "SVK"), sf.make_op("Q", 2, "SVK", nq1=4)):
         with pytest.raises(sf.SfError):
             sf.sf_element_dims(bad)
+
+
+def test_vector_family_dims_and_layout():
+    for p in range(1, 9):
+        n = p + 1
+        for form in ("MASS", "LAPLACE"):
+            op = sf.make_op("VQ", p, form)
+            assert sf.sf_element_dims(op) == (3 * n ** 3, n ** 3)
+            ext, off = sf.sf_block_layout(op)
+            assert ext == [[n, n, n]] * 3 and off == [0, n ** 3, 2 * n ** 3]
+    for bad in (sf.make_op("VQ", 2, "HDIV"), sf.make_op("VQ", 2, "MASS", precision="fp32"),
+                sf.make_op("VQ", 2, "MASS", io="f32"), sf.make_op("VQ", 9, "LAPLACE")):
+        with pytest.raises(sf.SfError):
+            sf.sf_element_dims(bad)
