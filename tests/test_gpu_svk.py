@@ -99,7 +99,7 @@ def test_svk_full_size_sampled(ctxs, p):
     """The bench's SVK workload (64^3 box cells, u0 0.01 N(0,1), du N(0,1) drawn on the
     GPU) in the bench's launch; evenly spaced cells recomputed by the oracle."""
     import torch
-    V = synth.box_mesh(64, 64, 64, 1)
+    V = synth.box_mesh(64, 64, 64, 2)
     n = len(V)
     nd = 3 * (p + 1) ** 3
     u0, du = synth.device_displacements(n, nd, 1, p)

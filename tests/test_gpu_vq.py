@@ -70,3 +70,22 @@ def test_vector_element_matrix_block_diagonal(ctxs, form, p):
                 assert not np.any(blk)
     ref = oracle.element_matrix("VQ", p, form, V, kappa=kap)
     assert rel_l2(Ah, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [2, 8])
+def test_vector_laplace_full_size_sampled(ctxs, p):
+    """The bench's vector Laplace workload (64^3 box cells, kappa and u drawn on the GPU) in
+    the bench's launch; evenly spaced cells recomputed by the oracle."""
+    import torch
+    V = synth.box_mesh(64, 64, 64, 2)
+    n = len(V)
+    n3 = (p + 1) ** 3
+    kap = synth.device_kappa(n, n3, 3, p)
+    _, u = synth.device_displacements(n, 3 * n3, 3, p)
+    y = torch.empty_like(u)
+    sf.assemble_action(ctxs["affine"], sf.make_op("VQ", p, "LAPLACE"), n, dev(V), kap, u, y)
+    assert sf.sf_check_errors(ctxs["affine"]) == 0
+    idx = np.linspace(0, n - 1, 6).astype(np.int64)
+    it = torch.from_numpy(idx).cuda()
+    ref = oracle.action("VQ", p, "LAPLACE", V[idx], host(u[it]), kappa=host(kap[it]))
+    assert max_cell_rel(host(y[it]), ref) <= 1e-11
