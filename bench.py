@@ -569,10 +569,16 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
 def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
     """Laplace action with lower-precision contractions (FP32 on the vector
     ALUs; BF16 / FP16 single term and BF16 x3 split on MFMA), geometry and
-    pointwise factors in FP64, against the FP64 GPU path on the same inputs
-    (FP64 storage): rate, speed-up and relative L2 difference."""
+    pointwise factors in FP64, against the FP64 GPU path on the same inputs:
+    rate, speed-up and relative L2 difference.  Rows without a suffix keep FP64
+    storage; rows "_f32io" also store kappa, u and y in FP32 (the inputs are
+    rounded once, outside the timed region, and the error is measured against
+    the FP64 result of the unrounded inputs, so it includes that rounding).
+    "best_le_1e-6" names, per degree, the fastest row within 1e-6."""
     import torch
 
+    modes = [("fp32", "f64"), ("bf16", "f64"), ("fp16", "f64"), ("bf16x3", "f64"), ("fp32", "f32"),
+             ("bf16x3", "f32")]
     out = {}
     for p in degrees:
         if p not in bufs:
@@ -581,25 +587,36 @@ def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
         ref = torch.empty_like(y)
         sf.assemble_action(ctx, sf.make_op("Q", p, "LAPLACE"), ncells, V, kap, u, ref, stream)
         row = {}
-        for mode in ("fp32", "bf16", "fp16", "bf16x3"):
-            op = sf.make_op("Q", p, "LAPLACE", precision=mode)
-            ym = torch.empty_like(y)
-            sf.assemble_action(ctx, op, ncells, V, kap, u, ym, stream)
+        for mode, io in modes:
+            op = sf.make_op("Q", p, "LAPLACE", precision=mode, io=io)
+            if io == "f32":
+                sets = [(k2.float(), u2.float()) for k2, u2, _ in bufs[p]]
+                ym = torch.empty(y.shape, dtype=torch.float32, device=y.device)
+            else:
+                sets = [(k2, u2) for k2, u2, _ in bufs[p]]
+                ym = torch.empty_like(y)
+            sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], ym, stream)
             torch.cuda.synchronize()
             ts = []
             for it in range(reps):
-                k2, u2, _ = bufs[p][it % len(bufs[p])]
+                k2, u2 = sets[it % len(sets)]
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(stream)
                 sf.assemble_action(ctx, op, ncells, V, k2, u2, ym, stream)
                 b.record(stream)
                 ts.append((a, b))
             torch.cuda.synchronize()
-            sf.assemble_action(ctx, op, ncells, V, kap, u, ym, stream)
-            err = float(torch.linalg.vector_norm(ym - ref) / torch.linalg.vector_norm(ref))
+            sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], ym, stream)
+            err = float(torch.linalg.vector_norm(ym.double() - ref) / torch.linalg.vector_norm(ref))
             t = float(np.mean([a.elapsed_time(b) for a, b in ts]))
-            row[mode] = {"ms": round(t, 4), "gdofs_global": round(glob[p] / (t / 1e3) / 1e9, 3),
-                         "speedup_vs_fp64": round(ms64[p] / t, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err)}
+            key = mode if io == "f64" else mode + "_f32io"
+            row[key] = {"ms": round(t, 4), "gdofs_global": round(glob[p] / (t / 1e3) / 1e9, 3),
+                        "speedup_vs_fp64": round(ms64[p] / t, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err)}
+            del sets, ym
+        ok = {k: v for k, v in row.items() if v["rel_l2_vs_fp64_gpu"] <= 1e-6}
+        if ok:
+            best = max(ok, key=lambda k: ok[k]["speedup_vs_fp64"])
+            row["best_le_1e-6"] = {"mode": best, "speedup_vs_fp64": ok[best]["speedup_vs_fp64"]}
         out[str(p)] = row
     return out
 
