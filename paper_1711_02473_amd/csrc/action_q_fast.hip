@@ -62,6 +62,9 @@ __global__ void __launch_bounds__(NT, MINB)
     __shared__ T lds[NB * C * CS];
     __shared__ double sP[C][6];
     __shared__ double sV[C][24];
+    // 1-D weights in LDS for the lane-dependent w[q] factors: a vector global load here
+    // would add a vector-memory wait to every stage that uses them
+    __shared__ T sWq[NQ];
     T *const L0 = lds;
     T *const L1 = lds + (NB - 1) * C * CS;
 
@@ -122,6 +125,7 @@ __global__ void __launch_bounds__(NT, MINB)
     const int64_t rounds = DYN ? (ngroups * 3 / 4) / gridDim.x : 0;
     const int parts = gridDim.x < 8 ? int(gridDim.x) : 8, part = int(blockIdx.x) % parts;
     int64_t g = blockIdx.x, gn = int64_t(blockIdx.x) + gridDim.x, it = 0;
+    if (tid < NQ) sWq[tid] = tW[tid]; // read after the loop's first barrier
     if (PREF && g < ngroups) {
         load_v(g);
         load_u(g);
@@ -183,7 +187,7 @@ __global__ void __launch_bounds__(NT, MINB)
             __syncthreads();
             if (pen && cell0 + pc < ncells) {
                 cptr<T> W = fresh(tW);
-                const T s23 = T(sP[pc][0]) * W[pa] * W[pb];
+                const T s23 = T(sP[pc][0]) * sWq[pa] * sWq[pb];
                 const int64_t base = (cell0 + pc) * N3 + pr;
                 T k[N];
                 ld_coeff(kappa, true, base, N2, k);
@@ -228,7 +232,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
                     apply_eo<N, false, false>(Bt, in, ut);
                     cptr<T> W = fresh(tW);
-                    const T w12 = T(sP[c][0]) * W[q1] * W[q2];
+                    const T w12 = T(sP[c][0]) * sWq[q1] * sWq[q2];
 #pragma unroll
                     for (int q3 = 0; q3 < NQ; ++q3) ut[q3] *= w12 * W[q3] * k[q3];
                     apply_eo<N, false, false>(BtT, ut, t);
@@ -251,7 +255,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     }
                     apply_eo<N, true, false>(Dh, ut, gz);
                     cptr<T> W = fresh(tW);
-                    const T w12 = T(sP[c][5]) * W[q1] * W[q2];
+                    const T w12 = T(sP[c][5]) * sWq[q1] * sWq[q2];
 #pragma unroll
                     for (int q3 = 0; q3 < NQ; ++q3) gz[q3] *= w12 * W[q3] * k[q3];
                     apply_eo<N, true, false>(DhT, gz, ut);
@@ -265,7 +269,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, ut);
                     apply_eo<N, true, false>(Dh, ut, gy);
                     cptr<T> W = fresh(tW);
-                    const T w13 = T(sP[c][3]) * W[q1] * W[q3];
+                    const T w13 = T(sP[c][3]) * sWq[q1] * sWq[q3];
 #pragma unroll
                     for (int q2 = 0; q2 < NQ; ++q2) gy[q2] *= w13 * W[q2] * k[q2];
                     ld_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
@@ -279,7 +283,7 @@ __global__ void __launch_bounds__(NT, MINB)
                     ld_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, ut);
                     apply_eo<N, true, false>(Dh, ut, gx);
                     cptr<T> W = fresh(tW);
-                    const T w23 = T(sP[pc][0]) * W[pa] * W[pb];
+                    const T w23 = T(sP[pc][0]) * sWq[pa] * sWq[pb];
 #pragma unroll
                     for (int q1 = 0; q1 < NQ; ++q1) gx[q1] *= w23 * W[q1] * kreg[q1];
                     ld_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
