@@ -56,6 +56,8 @@ def load():
                                ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp, dp, dp]
     lib.orc_svk.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                             ctypes.c_int, ctypes.c_long, dp, dp, dp, dp]
+    lib.orc_svk_matrix.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_long, dp, dp, dp]
     lib.orc_dofmap_q.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
     lib.orc_dofmap_q.restype = ctypes.c_long
     lib.orc_concat_index.argtypes = [ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, ip]
@@ -212,6 +214,25 @@ def svk_residual(family, degree, vertices, u0, lam, mu, nq1=0, check_geometry=Tr
 def svk_jacobian_action(family, degree, vertices, u0, du, lam, mu, nq1=0, check_geometry=True):
     """Action of the linearised residual at u0 on du: int dP(u0; du) : grad(psi_i e_c')."""
     return _svk(2, family, degree, vertices, u0, du, lam, mu, nq1, check_geometry)
+
+
+def svk_matrix(family, degree, vertices, u0, lam, mu, nq1=0, check_geometry=True):
+    """Element matrices of the linearised residual at u0, [ncells][3 ndof][3 ndof] (row = test),
+    from the tangent modulus of P at every point."""
+    m = _nq1(family, degree, nq1)
+    vertices = np.ascontiguousarray(vertices, dtype=np.float64)
+    ncells = vertices.shape[0]
+    nd = 3 * ndof(family, degree)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    assert u0.shape == (ncells, nd)
+    A = np.zeros((ncells, nd, nd))
+    rc = load().orc_svk_matrix(FAMILIES[family], degree, m, float(lam), float(mu), ncells, _dp(vertices), _dp(u0),
+                               _dp(A))
+    if rc < 0:
+        raise ValueError("oracle rejected arguments (%d)" % rc)
+    if rc > 0 and check_geometry:
+        raise ValueError("det J <= 0 in cell %d" % (rc - 1))
+    return A
 
 
 def dofmap_q(nx, ny, nz, p):

@@ -683,6 +683,99 @@ static void svk_point(double lambda, double mu, const double H[3][3], const doub
         }
 }
 
+/*
+ * Tangent modulus of the first Piola-Kirchhoff stress at F (dP = Amod : dF,
+ * dP_{ce} = sum_{c'e'} Amod[c][e][c'][e'] dF_{c'e'}), from differentiating
+ * P = F S(E(F)) term by term:
+ *   Amod = delta_{cc'} S_{e'e} + lambda F_{ce} F_{c'e'}
+ *          + mu ((F F^T)_{cc'} delta_{ee'} + F_{ce'} F_{c'e}).
+ */
+static void svk_tangent(double lambda, double mu, const double H[3][3], double Amod[3][3][3][3])
+{
+    double F[3][3], E[3][3], S[3][3], FFt[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) F[a][b] = (a == b ? 1.0 : 0.0) + H[a][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double c = 0.0, d = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                c += F[k][a] * F[k][b];
+                d += F[a][k] * F[b][k];
+            }
+            E[a][b] = 0.5 * (c - (a == b ? 1.0 : 0.0));
+            FFt[a][b] = d;
+        }
+    double trE = E[0][0] + E[1][1] + E[2][2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = (a == b ? lambda * trE : 0.0) + 2.0 * mu * E[a][b];
+    for (int c = 0; c < 3; ++c)
+        for (int e = 0; e < 3; ++e)
+            for (int cc = 0; cc < 3; ++cc)
+                for (int ee = 0; ee < 3; ++ee)
+                    Amod[c][e][cc][ee] = (c == cc ? S[ee][e] : 0.0) + lambda * F[c][e] * F[cc][ee] +
+                                         mu * (FFt[c][cc] * (e == ee ? 1.0 : 0.0) + F[c][ee] * F[cc][e]);
+}
+
+/*
+ * Element matrices of the linearised residual at u0 (the bilinear form with
+ * trial function du, test function v):
+ *   A[c][(c',i)][(c'',j)] = sum_q w |det J| sum_{e,e'} dPsi_i/dx_e Amod[c'][e][c''][e'] dPsi_j/dx_e'
+ * [ncells][3 nd][3 nd], row = test.  Returns as orc_action.
+ */
+int orc_svk_matrix(int family, int degree, int nq1, double lambda, double mu, long ncells,
+                   const double *vertices, const double *u0, double *A)
+{
+    if (family != ORC_Q && family != ORC_QGLL) return -2;
+    orc_setup s;
+    int rc = setup(family, degree, ORC_LAPLACE, nq1, &s);
+    if (rc) return rc;
+    const int nd = s.e.ndof, nq = s.nq, NDV = 3 * nd;
+    long bad = -1;
+#pragma omp parallel
+    {
+        double *f = (double *)malloc(sizeof(double) * (size_t)nd * ORC_SLOTS);
+#pragma omp for schedule(dynamic, 1)
+        for (long c = 0; c < ncells; ++c) {
+            const double *X = vertices + c * 24;
+            const double *uc = u0 + (size_t)c * NDV;
+            double *Ac = A + (size_t)c * NDV * NDV;
+            for (size_t t = 0; t < (size_t)NDV * NDV; ++t) Ac[t] = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                double xi[3], w, J[3][3], G[3][3];
+                point(&s, q, xi, &w);
+                jacobian(X, xi, J);
+                double det = det3(J);
+                if (det <= 0.0) {
+#pragma omp critical
+                    if (bad < 0 || c < bad) bad = c;
+                }
+                inverse3(J, det, G);
+                push_forward(&s.e, s.val + (size_t)q * nd * 3, s.grad + (size_t)q * nd * 9, J, G, det, f);
+                double H[3][3] = {{0}};
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int i = 0; i < nd; ++i)
+                        for (int a = 0; a < 3; ++a) H[cc][a] += uc[cc * nd + i] * f[i * ORC_SLOTS + 1 + a];
+                double Amod[3][3][3][3];
+                svk_tangent(lambda, mu, H, Amod);
+                double sc = w * fabs(det);
+                for (int c1 = 0; c1 < 3; ++c1)
+                    for (int c2 = 0; c2 < 3; ++c2)
+                        for (int i = 0; i < nd; ++i)
+                            for (int j = 0; j < nd; ++j) {
+                                double t = 0.0;
+                                for (int e = 0; e < 3; ++e)
+                                    for (int ee = 0; ee < 3; ++ee)
+                                        t += f[i * ORC_SLOTS + 1 + e] * Amod[c1][e][c2][ee] * f[j * ORC_SLOTS + 1 + ee];
+                                Ac[(size_t)(c1 * nd + i) * NDV + c2 * nd + j] += sc * t;
+                            }
+            }
+        }
+        free(f);
+    }
+    teardown(&s);
+    return bad >= 0 ? (int)(1 + (bad > 2000000000L ? 2000000000L : bad)) : 0;
+}
+
 int orc_svk(int family, int degree, int nq1, double lambda, double mu, int mode, long ncells,
             const double *vertices, const double *u0, const double *du, double *out)
 {

@@ -36,6 +36,8 @@ MUTANTS = [
     ("for (int b = 0; b < 3; ++b) s += g[3 * c + b] * G[b][a]; /* d v_c / d x_a */",
      "for (int b = 0; b < 3; ++b) s += g[3 * c + b] * G[a][b];", "vector element: G transposed"),
     ("e->b[c].offset = c * n * n * n;", "e->b[c].offset = 0;", "vector element: blocks overlap"),
+    ("mu * (FFt[c][cc] * (e == ee ? 1.0 : 0.0) + F[c][ee] * F[cc][e]);",
+     "mu * (FFt[c][cc] * (e == ee ? 1.0 : 0.0) + F[c][e] * F[cc][ee]);", "SVK tangent: swapped indices"),
 ]
 PIN_SUITES = [os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_golden.py"),
               os.path.join(ROOT, "tests", "test_oracle_svk.py"), os.path.join(ROOT, "tests", "test_oracle_vq.py")]

@@ -157,3 +157,19 @@ def test_linearisation_at_rest_is_linear_elasticity(family, p, kind):
         # rigid translations are in the kernel of the linearised form at rest
         t = linear_field(family, p, V[c], np.zeros((3, 3)), t=np.array([1.0, 2.0, -3.0]))[None, :]
         assert np.abs(oracle.svk_jacobian_action(family, p, V[c:c + 1], zero, t, LAM, MU)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("family,p,kind", CASES[:5])
+def test_tangent_matrix_applies_as_the_linearised_residual(family, p, kind):
+    """The element matrix from the tangent modulus, times du, equals the linearised
+    residual (itself pinned above as the exact derivative of the residual), and is
+    symmetric (the Hessian of the energy)."""
+    V = cells(kind, 3, 90 + p)
+    nd = 3 * (p + 1) ** 3
+    rng = np.random.default_rng(17 + p)
+    u = 0.1 * rng.standard_normal((3, nd))
+    v = rng.standard_normal((3, nd))
+    A = oracle.svk_matrix(family, p, V, u, LAM, MU)
+    a = oracle.svk_jacobian_action(family, p, V, u, v, LAM, MU)
+    assert np.allclose(np.einsum("cij,cj->ci", A, v), a, rtol=1e-11, atol=1e-12 * np.abs(a).max())
+    assert np.allclose(A, np.transpose(A, (0, 2, 1)), rtol=1e-12, atol=1e-13 * np.abs(A).max())
