@@ -401,6 +401,20 @@ def svk_leg(sf, ctx, V, degrees, reps, stream, lam=1.3, mu=0.8):
                        "gdofs_global": round(3 * (64 * p + 1) ** 3 / (ms / 1e3) / 1e9, 3),
                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
         del sets, y
+        if p <= 4:
+            # element matrices of the linearised residual (left-hand-side assembly), first 4096
+            # cells; algorithmic work per cell: 9 blocks x 2 (4 n^7 + 18 n^6 + 9 n^5) flops
+            n, nm = p + 1, 4096
+            u0 = synth.device_displacements(nm, 3 * n3, 1, p)[0]
+            A = torch.empty((nm, 3 * n3, 3 * n3), dtype=torch.float64, device="cuda")
+            sf.assemble_element_matrix(ctx, op, nm, V[:nm], u0, A, stream)
+            ms = timed(lambda it: sf.assemble_element_matrix(ctx, op, nm, V[:nm], u0, A, stream), reps, stream)
+            gbs = nm * 8 * (3 * n3) ** 2 / (ms / 1e3) / 1e9
+            fl = nm * 18 * (4 * n ** 7 + 18 * n ** 6 + 9 * n ** 5)
+            out["matrix_%d" % p] = {"ms": round(ms, 4), "cells": nm, "hbm_gbs": round(gbs, 1),
+                                    "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                                    "fp64_tflops": round(fl / (ms / 1e3) / 1e12, 2)}
+            del A, u0
     assert sf.sf_check_errors(ctx) == 0
     return out
 

@@ -105,9 +105,12 @@ enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3, SF_SVK = 4, SF_SV
  *                    in `kappa` (the form's coefficient) as a local vector of
  *                    the same layout, NULL for u0 = 0 (linear elasticity).
  * Quadrature: p+1 points per axis (GL for SF_Q, GLL for SF_QGLL).  FP64
- * contractions and SF_F64 storage only; action only (element matrices
- * return SF_ERR_UNSUPPORTED).  Geometry: affine cells, or any trilinear cell
- * under SF_GEOM_TRILINEAR (J per point). */
+ * contractions and SF_F64 storage only.  Element matrices: SF_SVK only, p <=
+ * 4 (SF_ERR_UNSUPPORTED otherwise), kappa = u0 as for the action, output
+ * [ncells][ndof_cell][ndof_cell] with row = test function (c, i) and column
+ * = trial function (c', j): the tangent modulus of P at u0 in every block.
+ * Geometry: affine cells, or any trilinear cell under SF_GEOM_TRILINEAR (J
+ * per point). */
 /* contraction precision: FP64, FP32 (both VALU); BF16 / FP16 single-term MFMA
  * with FP32 accumulation; BF16X3 = operands split into three BF16 terms
  * (hi + mid + lo), six cross products per contraction, FP32 accumulation.
@@ -216,7 +219,8 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
  *   A[c][i][j] = a(psi_j, psi_i) on cell c, row i = test, column j = trial,
  *   device [ncells][ndof_cell][ndof_cell] io_dtype, overwritten.
  * Other arguments and errors as assemble_action().  Cells must be
- * axis-aligned boxes.
+ * axis-aligned boxes, except for SF_SVK (affine or, under
+ * SF_GEOM_TRILINEAR, trilinear cells).
  */
 int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
                             const void *kappa, void *A, void *hip_stream);

@@ -430,13 +430,18 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
     Dims d;
     int rc = check_op(op, &d);
     if (rc) return rc;
-    if (op->precision != SF_FP64 || svk_form(op->form)) return SF_ERR_UNSUPPORTED;
+    if (op->precision != SF_FP64 || op->form == SF_SVK_RESIDUAL) return SF_ERR_UNSUPPORTED;
+    if (op->form == SF_SVK && op->degree > 4) return SF_ERR_UNSUPPORTED;
     if (ncells == 0) return SF_OK;
     if (!vertices || !A || A == kappa) return SF_ERR_ARG;
     LaunchArgs a;
     rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
     if (rc) return rc;
     a.A = A;
+    if (op->form == SF_SVK) {
+        a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
+        return launch_matrix_svk(a);
+    }
     if (scalar_family(op->family) || op->family == SF_VQ) return launch_matrix_q(a);
     return launch_matrix_vec(a);
 }

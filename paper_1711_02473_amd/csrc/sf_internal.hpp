@@ -97,6 +97,7 @@ constexpr int kSchedSlots = 256;
 // kernel launchers: return SF_OK, SF_ERR_UNSUPPORTED or SF_ERR_HIP
 int launch_action_q(const LaunchArgs &a);
 int launch_action_vq(const LaunchArgs &a);
+int launch_matrix_svk(const LaunchArgs &a);
 int launch_action_q_fast(const LaunchArgs &a);
 int launch_action_q_global(const LaunchArgs &a, int nx, int ny, int nz);
 int launch_matrix_q(const LaunchArgs &a);

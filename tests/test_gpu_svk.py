@@ -82,16 +82,13 @@ def test_svk_flags_and_rejections(ctxs):
     V[1, 7] = V[1, 0] - 0.9 * (V[1, 7] - V[1, 0])
     _, f = run(ctxs["trilinear"], op, V, u0, du)
     assert f & sf.SF_FLAG_DETJ
-    # residual takes no coefficient; FP32 and element matrices are not built; DQ has no vector form
+    # residual takes no coefficient; FP32 is not built; DQ has no vector form
     with pytest.raises(sf.SfError):
         run(ctxs["affine"], sf.make_op("Q", p, "SVK_RESIDUAL", alpha=LAM, beta=MU), synth.affine_cells(n, 94), u0, du)
     with pytest.raises(sf.SfError):
         run(ctxs["affine"], sf.make_op("Q", p, "SVK", precision="fp32"), synth.affine_cells(n, 94), u0, du)
     with pytest.raises(sf.SfError):
         sf.sf_element_dims(sf.make_op("DQ", p, "SVK"))
-    A = empty((n, nd, nd), np.float64)
-    with pytest.raises(sf.SfError):
-        sf.assemble_element_matrix(ctxs["affine"], op, n, dev(synth.affine_cells(n, 94)), None, A)
 
 
 @pytest.mark.parametrize("p", [2, 4, 8])
@@ -111,3 +108,34 @@ def test_svk_full_size_sampled(ctxs, p):
     it = torch.from_numpy(idx).cuda()
     ref = oracle.svk_jacobian_action("Q", p, V[idx], host(u0[it]), host(du[it]), LAM, MU)
     assert max_cell_rel(host(y[it]), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("geom", ["affine", "trilinear"])
+@pytest.mark.parametrize("family", ["Q", "QGLL"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_svk_element_matrix_matches_oracle(ctxs, geom, family, p):
+    n = {1: 9, 2: 5, 3: 3, 4: 2}[p]
+    V = synth.affine_cells(n, 150 + p) if geom == "affine" else synth.trilinear_cells(n, 150 + p)
+    nd = 3 * (p + 1) ** 3
+    u0, du = synth.displacements(n, nd, 150 + p, amp=0.05)
+    op = sf.make_op(family, p, "SVK", alpha=LAM, beta=MU)
+    print("case svk matrix", geom, family, p, flush=True)
+    A = empty((n, nd, nd), np.float64)
+    sf.assemble_element_matrix(ctxs[geom], op, n, dev(V), dev(u0), A)
+    assert sf.sf_check_errors(ctxs[geom]) == 0
+    Ah = host(A)
+    ref = oracle.svk_matrix(family, p, V, u0, LAM, MU)
+    assert rel_l2(Ah, ref) <= 1e-12
+    # the matrix applied to du is the GPU's own linearised action
+    y, f = run(ctxs[geom], op, V, u0, du)
+    assert f == 0
+    assert rel_l2(np.einsum("cij,cj->ci", Ah, du), y) <= 1e-12
+
+
+def test_svk_element_matrix_limits(ctxs):
+    V = synth.affine_cells(2, 160)
+    for op in (sf.make_op("Q", 5, "SVK"), sf.make_op("Q", 2, "SVK_RESIDUAL")):
+        nd, _ = sf.sf_element_dims(op)
+        A = empty((2, nd, nd), np.float64)
+        with pytest.raises(sf.SfError):
+            sf.assemble_element_matrix(ctxs["affine"], op, 2, dev(V), None, A)
