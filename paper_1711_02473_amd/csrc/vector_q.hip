@@ -67,10 +67,10 @@ template <int N, int C, int NF, int NT, typename Fn> __device__ __forceinline__ 
     }
 }
 
-// Two independent pencil stages over the same fields, one along axis 1 (f1) and
-// one along axis 2 (f2), run as one loop so that all threads have work.
+// Two independent pencil stages over the same fields (each lambda loads and stores
+// along its own axis), run as one loop so that all threads have work.
 template <int N, int C, int NF, int NT, typename F1, typename F2>
-__device__ __forceinline__ void vq_pencils_12(F1 &&f1, F2 &&f2)
+__device__ __forceinline__ void vq_pencils_2(F1 &&f1, F2 &&f2)
 {
     constexpr int NP = N * N, PER = NF * NP, TOT = C * PER;
     for (int t = threadIdx.x; t < 2 * TOT; t += NT) {
@@ -195,59 +195,66 @@ __global__ void __launch_bounds__(vq_nt(N, FORM))
     constexpr int C = Sh::C, NF = Sh::NF, NS = Sh::NS, SPF = Sh::SPF, NT = Sh::NT, N3 = N * N * N;
     constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
     constexpr TabLayout TL(N, 0, N);
-    // inputs of one group: C * NF * N3 field values, then C * 24 vertex coordinates
-    constexpr int NFLD = C * NF * N3, NIN = NFLD + C * 24, K = (NIN + NT - 1) / NT;
+    constexpr int N2 = N * N;
+    // inputs of one group: the C * NF * N2 axis-0 lines (x-pencils) of the fields, N values
+    // each, and C * 24 vertex coordinates
+    constexpr int NPEN = C * NF * N2, KP = (NPEN + NT - 1) / NT, KV = (C * 24 + NT - 1) / NT;
     __shared__ double smem[C * Sh::CELL];
     double *geo = smem;              // [C][GEO]: vertices (24), G (9), |det J|
     double *ts = smem + C * Sh::GEO; // [C][NS][CS], field f: slots SPF f (values / d0), SPF f + 1 (d1), + 2 (d2)
     auto tensor = [&](int c, int s) { return ts + (c * NS + s) * CS; };
     const int64_t ngroups = (ncells + C - 1) / C;
+    const double *BE = tab + TL.BEO(), *BTE = tab + TL.BTEO();
 
-    // This thread's share of a group's inputs, requested in one unrolled batch
-    // (every lane loads; lanes without an element read vert[0] and discard it).
-    // Fields f < 3 are component f of f0, f >= 3 component f - 3 of f1 (zero when
-    // the array is NULL); padding cells get zero fields and the unit cube.
-    double pf[K];
+    // This thread's share of a group's inputs, requested in one unrolled batch: x-pencils
+    // (lanes on consecutive pencils read consecutive addresses) and vertex coordinates.
+    // Every lane loads (lanes without data read vert[0] and discard it).  Fields f < 3 are
+    // component f of f0, f >= 3 component f - 3 of f1 (zero when the array is NULL);
+    // padding cells get zero fields and the unit cube.
+    double pf[KP][N], pv[KV];
     auto fetch = [&](int64_t g) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < KP; ++k) {
             const int t = threadIdx.x + k * NT;
-            const double *src = vert;
-            double fill = 0.0;
-            bool ok = false;
-            if (t < NFLD) {
-                const int c = t / (NF * N3);
-                const int r = t - c * NF * N3;
-                const int f = r / N3;
-                const double *base = f < 3 ? f0 : f1;
-                ok = base != nullptr && g * C + c < ncells;
-                if (ok) src = base + (g * C + c) * (3 * N3) + (f % 3) * N3 + (r - f * N3);
-            } else if (t < NIN) {
-                const int c = (t - NFLD) / 24, e = (t - NFLD) - c * 24;
-                const int v = e / 3, ax = e - v * 3;
-                fill = ((v >> (2 - ax)) & 1) ? 1.0 : 0.0;
-                ok = g * C + c < ncells;
-                if (ok) src = vert + (g * C + c) * 24 + e;
+            const int c = t / (NF * N2), r = t - c * (NF * N2), f = r / N2;
+            const double *base = f < 3 ? f0 : f1;
+            const bool ok = t < NPEN && base != nullptr && g * C + c < ncells;
+            const double *src = ok ? base + (g * C + c) * (3 * N3) + (f % 3) * N3 + (r - f * N2) : vert;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const double x = src[ok ? i * N2 : 0];
+                pf[k][i] = ok ? x : 0.0;
             }
-            const double x = *src;
-            pf[k] = ok ? x : fill;
+        }
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
+            const int t = threadIdx.x + k * NT;
+            const int c = t / 24, e = t - c * 24, v = e / 3, ax = e - v * 3;
+            const bool ok = t < C * 24 && g * C + c < ncells;
+            const double x = vert[ok ? (g * C + c) * 24 + e : 0];
+            pv[k] = ok ? x : (((v >> (2 - ax)) & 1) ? 1.0 : 0.0);
         }
     };
+    // the x-pencils go to LDS already interpolated along axis 0 (B_0 in registers)
     auto stash = [&]() {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < KP; ++k) {
             const int t = threadIdx.x + k * NT;
-            if (t < NFLD) {
-                const int c = t / (NF * N3);
-                const int r = t - c * NF * N3;
-                const int f = r / N3;
-                const int i = r - f * N3;
-                const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
-                tensor(c, SPF * f)[i0 * S1 + i1 * S2 + i2] = pf[k];
-            } else if (t < NIN) {
-                const int c = (t - NFLD) / 24;
-                geo[c * Sh::GEO + (t - NFLD - c * 24)] = pf[k];
+            if (t < NPEN) {
+                const int c = t / (NF * N2), r = t - c * (NF * N2), f = r / N2, pr = r - f * N2;
+                if constexpr (COLL) {
+                    st_pencil<0, N, S1, S2>(tensor(c, SPF * f), pr / N, pr % N, pf[k]);
+                } else {
+                    double o[N];
+                    apply_eo<N, false, false>(BE, pf[k], o);
+                    st_pencil<0, N, S1, S2>(tensor(c, SPF * f), pr / N, pr % N, o);
+                }
             }
+        }
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
+            const int t = threadIdx.x + k * NT;
+            if (t < C * 24) geo[(t / 24) * Sh::GEO + t % 24] = pv[k];
         }
     };
 
@@ -274,16 +281,11 @@ __global__ void __launch_bounds__(vq_nt(N, FORM))
             }
         }
 
-        // interpolation to the Gauss points, one axis at a time, in place
+        // forward: interpolation along axis 1, then along axis 2 fused with the axis-2
+        // derivative (written to its own tensor); then the axis-1 derivative and, once
+        // every read of the values is done, the axis-0 derivative in place
+        const double *DE = tab + TL.DhEO();
         if constexpr (!COLL) {
-            const double *BE = tab + TL.BEO();
-            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-                double x[N], o[N];
-                ld_pencil<0, N, S1, S2>(tensor(c, SPF * f), a, b, x);
-                apply_eo<N, false, false>(BE, x, o);
-                st_pencil<0, N, S1, S2>(tensor(c, SPF * f), a, b, o);
-            });
-            __syncthreads();
             vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
                 double x[N], o[N];
                 ld_pencil<1, N, S1, S2>(tensor(c, SPF * f), a, b, x);
@@ -291,30 +293,30 @@ __global__ void __launch_bounds__(vq_nt(N, FORM))
                 st_pencil<1, N, S1, S2>(tensor(c, SPF * f), a, b, o);
             });
             __syncthreads();
-            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
-                double x[N], o[N];
-                ld_pencil<2, N, S1, S2>(tensor(c, SPF * f), a, b, x);
+        }
+        vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+            double x[N], o[N];
+            ld_pencil<2, N, S1, S2>(tensor(c, SPF * f), a, b, x);
+            if constexpr (!COLL) {
                 apply_eo<N, false, false>(BE, x, o);
                 st_pencil<2, N, S1, S2>(tensor(c, SPF * f), a, b, o);
-            });
-            __syncthreads();
-        }
-        // reference gradients: axes 1 and 2 into their own tensors, then axis 0 in place
+            } else {
+#pragma unroll
+                for (int j = 0; j < N; ++j) o[j] = x[j];
+            }
+            if constexpr (GRAD) {
+                apply_eo<N, true, false>(DE, o, x);
+                st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, x);
+            }
+        });
+        __syncthreads();
         if constexpr (GRAD) {
-            const double *DE = tab + TL.DhEO();
-            vq_pencils_12<N, C, NF, NT>(
-                [&](int c, int f, int a, int b) {
-                    double x[N], o[N];
-                    ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-                    apply_eo<N, true, false>(DE, x, o);
-                    st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
-                },
-                [&](int c, int f, int a, int b) {
-                    double x[N], o[N];
-                    ld_pencil<2, N, S1, S2>(tensor(c, 3 * f), a, b, x);
-                    apply_eo<N, true, false>(DE, x, o);
-                    st_pencil<2, N, S1, S2>(tensor(c, 3 * f + 2), a, b, o);
-                });
+            vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
+                double x[N], o[N];
+                ld_pencil<1, N, S1, S2>(tensor(c, 3 * f), a, b, x);
+                apply_eo<N, true, false>(DE, x, o);
+                st_pencil<1, N, S1, S2>(tensor(c, 3 * f + 1), a, b, o);
+            });
             __syncthreads();
             vq_pencils<N, C, NF, NT>([&](int c, int f, int a, int b) {
                 double x[N], o[N];
@@ -379,47 +381,47 @@ __global__ void __launch_bounds__(vq_nt(N, FORM))
         }
         __syncthreads();
 
-        // back to the DOFs: Dh^T along axes 1 and 2 in place, then along axis 0 with the
-        // three directions summed (and B^T applied on the same pencil), then B^T along 1, 2
-        const double *BTE = tab + TL.BTEO();
+        // back to the DOFs: Dh^T along axes 0 and 1 in place; along axis 2 the three
+        // directions summed (and B^T_2 applied on the same pencil); B^T_1; then B^T_0 on
+        // x-pencils straight into y (lanes on consecutive pencils, coalesced)
         if constexpr (GRAD) {
             const double *DTE = tab + TL.DhTEO();
-            vq_pencils_12<N, C, 3, NT>(
+            vq_pencils_2<N, C, 3, NT>(
+                [&](int c, int k, int a, int b) {
+                    double x[N], o[N];
+                    ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                    apply_eo<N, true, false>(DTE, x, o);
+                    st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+                },
                 [&](int c, int k, int a, int b) {
                     double x[N], o[N];
                     ld_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
                     apply_eo<N, true, false>(DTE, x, o);
                     st_pencil<1, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
-                },
-                [&](int c, int k, int a, int b) {
-                    double x[N], o[N];
-                    ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
-                    apply_eo<N, true, false>(DTE, x, o);
-                    st_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, o);
                 });
             __syncthreads();
             vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
-                ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 1), a, b, o);
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, o);
                 apply_eo<N, true, true>(DTE, x, o);
-                ld_pencil<0, N, S1, S2>(tensor(c, 3 * k + 2), a, b, x);
+                ld_pencil<2, N, S1, S2>(tensor(c, 3 * k + 1), a, b, x);
 #pragma unroll
                 for (int j = 0; j < N; ++j) o[j] += x[j];
                 if constexpr (!COLL) {
                     apply_eo<N, false, false>(BTE, o, x);
-                    st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, x);
+                    st_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, x);
                 } else {
-                    st_pencil<0, N, S1, S2>(tensor(c, 3 * k), a, b, o);
+                    st_pencil<2, N, S1, S2>(tensor(c, 3 * k), a, b, o);
                 }
             });
             __syncthreads();
         } else if constexpr (!COLL) {
             vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
                 double x[N], o[N];
-                ld_pencil<0, N, S1, S2>(tensor(c, SPF * k), a, b, x);
+                ld_pencil<2, N, S1, S2>(tensor(c, SPF * k), a, b, x);
                 apply_eo<N, false, false>(BTE, x, o);
-                st_pencil<0, N, S1, S2>(tensor(c, SPF * k), a, b, o);
+                st_pencil<2, N, S1, S2>(tensor(c, SPF * k), a, b, o);
             });
             __syncthreads();
         }
@@ -431,22 +433,21 @@ __global__ void __launch_bounds__(vq_nt(N, FORM))
                 st_pencil<1, N, S1, S2>(tensor(c, SPF * k), a, b, o);
             });
             __syncthreads();
-            vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
-                double x[N], o[N];
-                ld_pencil<2, N, S1, S2>(tensor(c, SPF * k), a, b, x);
+        }
+        vq_pencils<N, C, 3, NT>([&](int c, int k, int a, int b) {
+            if (cell0 + c >= ncells) return;
+            double x[N], o[N];
+            ld_pencil<0, N, S1, S2>(tensor(c, SPF * k), a, b, x);
+            if constexpr (!COLL) {
                 apply_eo<N, false, false>(BTE, x, o);
-                st_pencil<2, N, S1, S2>(tensor(c, SPF * k), a, b, o);
-            });
-            __syncthreads();
-        }
-        for (int t = threadIdx.x; t < C * 3 * N3; t += NT) {
-            const int c = t / (3 * N3);
-            const int r = t - c * 3 * N3;
-            const int k = r / N3;
-            const int i = r - k * N3;
-            const int i0 = i / (N * N), i1 = (i / N) % N, i2 = i % N;
-            if (cell0 + c < ncells) y[(cell0 + c) * (3 * N3) + r] = tensor(c, SPF * k)[i0 * S1 + i1 * S2 + i2];
-        }
+            } else {
+#pragma unroll
+                for (int j = 0; j < N; ++j) o[j] = x[j];
+            }
+            double *yo = y + (cell0 + c) * (3 * N3) + k * N3 + a * N + b;
+#pragma unroll
+            for (int i0 = 0; i0 < N; ++i0) yo[i0 * N2] = o[i0];
+        });
         __syncthreads(); // the next group overwrites the tensors
     }
 }
