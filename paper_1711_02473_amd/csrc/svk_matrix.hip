@@ -18,8 +18,9 @@
 // nine products fall into four groups by their axis-0 pair (B or D for the
 // test and trial functions), so the last stage runs four sweeps, not nine.
 //
-// Mapping: one workgroup per (cell, block).  The cell's u0 is staged in LDS
-// and its gradient evaluated at each point directly (O(n^6) per block, small
+// Mapping: one workgroup per (cell, block), one thread per column of the block
+// for p <= 3 (one wave), so that the last stage keeps every lane busy.  The cell's u0 is staged in LDS and its gradient evaluated at
+// each point directly (O(n^6) per block, small
 // beside the O(n^7) matrix stages at these degrees); the block's nine
 // coefficient fields K then stay in LDS for the matrix stages.  Rows of the
 // block are written as contiguous (p+1)^3-long runs.
@@ -28,17 +29,21 @@
 
 namespace sf {
 
+// threads per workgroup: one per column j of a block row, (p+1)^3 rounded up to a
+// wave, for p <= 3; 256 for p = 4, where the first two stages' extra threads pay more
+// than the idle lanes of the last one cost (measured)
+__host__ __device__ constexpr int svk_matrix_nt(int n) { return n <= 4 ? (n * n * n + 63) / 64 * 64 : 256; }
+
 template <int N, bool TRI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(svk_matrix_nt(N))
     svk_matrix_kernel(const int64_t ncells, const double *__restrict__ vert, const double *__restrict__ u0,
                       double *__restrict__ A, const double *__restrict__ tab, const double lambda, const double mu,
                       int *__restrict__ err)
 {
-    constexpr int NT = 256, N2 = N * N, N3 = N2 * N, ND = 3 * N3;
+    constexpr int NT = svk_matrix_nt(N), N2 = N * N, N3 = N2 * N, ND = 3 * N3;
     constexpr TabLayout TL(N, 0, N);
     constexpr int T1SZ = N * N * N; // one i2-slice of one product: [q0][q1][j2]
     constexpr int T2SZ = N * N * N; // one group: [q0][j1][j2]
-    static_assert(9 * N2 <= NT, "one stage-1 line per thread");
     __shared__ double sU[3 * N3];      // u0 by component
     __shared__ double sB[N * N];       // B[q][i]
     __shared__ double sD[N * N];       // D[q][i]
@@ -158,12 +163,11 @@ __global__ void __launch_bounds__(256)
 
     // ---- sum-factorised products, merged by their axis-0 pair in the last stage
     const int64_t rowbase = cell * int64_t(ND) * ND + int64_t(cr * N3) * ND + cc * N3;
-    // stage-1 line of this thread: product p1, (q0, q1)
-    const bool has1 = tid < 9 * N2;
-    const int p1 = has1 ? tid / N2 : 0, q01 = tid - p1 * N2;
-    const int d1 = p1 / 3, dd1 = p1 - d1 * 3;
     for (int i2 = 0; i2 < N; ++i2) {
-        if (has1) {
+        // stage 1: one line per task, product p1 and (q0, q1)
+        for (int t = tid; t < 9 * N2; t += NT) {
+            const int p1 = t / N2, q01 = t - p1 * N2;
+            const int d1 = p1 / 3, dd1 = p1 - d1 * 3;
             const double *X = d1 == 2 ? sD : sB;  // test table on axis 2
             const double *Y = dd1 == 2 ? sD : sB; // trial table on axis 2
             const double *k = sK + p1 * N3 + q01 * N;
@@ -238,9 +242,9 @@ template <int N, bool TRI> int launch_svk_matrix_n(const LaunchArgs &a)
 {
     const int64_t groups = a.ncells * 9;
     if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
-    hipLaunchKernelGGL((svk_matrix_kernel<N, TRI>), dim3(unsigned(groups)), dim3(256), 0, a.stream, a.ncells, a.vert,
-                       static_cast<const double *>(a.kappa), static_cast<double *>(a.A), a.tab64, a.alpha, a.beta,
-                       a.err);
+    hipLaunchKernelGGL((svk_matrix_kernel<N, TRI>), dim3(unsigned(groups)), dim3(svk_matrix_nt(N)), 0, a.stream,
+                       a.ncells, a.vert, static_cast<const double *>(a.kappa), static_cast<double *>(a.A), a.tab64,
+                       a.alpha, a.beta, a.err);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
