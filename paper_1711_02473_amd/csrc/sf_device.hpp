@@ -285,6 +285,38 @@ __device__ inline double trilinear_jacobian(const double *__restrict__ X, double
            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
+// The same Jacobian along a line of reference points on which only coordinate
+// AX varies (the other two fixed at xa < xb's axes order, i.e. xa on the lower
+// of the two other axes): the map is linear in each reference coordinate, so
+// J(t) = Ja + t Jb, column AX of Jb being zero.  One evaluation per line
+// instead of one per point.
+template <int AX>
+__device__ inline void trilinear_line(const double *__restrict__ X, double xa, double xb, double Ja[3][3],
+                                      double Jb[3][3])
+{
+    constexpr int D1 = AX == 0 ? 1 : 0, D2 = AX == 2 ? 1 : 2; // the fixed axes, D1 < D2
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Ja[a][b] = Jb[a][b] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int bit[3] = {v >> 2, (v >> 1) & 1, v & 1};
+        const double s1 = bit[D1] ? 1.0 : -1.0, s2 = bit[D2] ? 1.0 : -1.0, sx = bit[AX] ? 1.0 : -1.0;
+        const double f1 = bit[D1] ? xa : 1.0 - xa, f2 = bit[D2] ? xb : 1.0 - xb;
+        const double ax0 = bit[AX] ? 0.0 : 1.0; // the AX factor is ax0 + sx t
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double xv = X[3 * v + a];
+            Ja[a][AX] = fma(xv, sx * f1 * f2, Ja[a][AX]);
+            Ja[a][D1] = fma(xv, s1 * f2 * ax0, Ja[a][D1]);
+            Jb[a][D1] = fma(xv, s1 * f2 * sx, Jb[a][D1]);
+            Ja[a][D2] = fma(xv, s2 * f1 * ax0, Ja[a][D2]);
+            Jb[a][D2] = fma(xv, s2 * f1 * sx, Jb[a][D2]);
+        }
+    }
+}
+
 // Affine cell geometry from the 8 vertices (vector-Q1 coordinate field with
 // the delta-cancelled scalar Q1 table, Sec. 3.1, evaluated for an affine map):
 // J = [x(1,0,0)-x0, x(0,1,0)-x0, x(0,0,1)-x0]; the remaining vertices must be
