@@ -427,7 +427,7 @@ int launch_global_n(const LaunchArgs &a, int ny, int nz, int64_t nglobal)
     constexpr int C = NT / (N * N) > 0 ? NT / (N * N) : 1;
     static int cache = 0;
     const int64_t groups = (a.ncells + C - 1) / C;
-    auto kern = action_q_fast_kernel<N, N, FORM, false, double, double, C, NT, false, 3, true>;
+    auto kern = action_q_fast_kernel<N, N, FORM, false, double, double, C, NT, true, 3, true>;
     const int grid = grid_for(kern, NT, groups, &cache);
     if (grid < 0 || !a.sched) return SF_ERR_HIP;
     // clear with a kernel (also inside captured graphs), then accumulate
