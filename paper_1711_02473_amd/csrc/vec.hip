@@ -101,6 +101,8 @@ __global__ void __launch_bounds__(NT)
 
     __shared__ T lds[NTEN * C * CS];
     __shared__ double sG[C][13];
+    __shared__ T sWq[NQ]; // 1-D weights (lane-dependent reads in the pointwise stage)
+    if (threadIdx.x < NQ) sWq[threadIdx.x] = tW[threadIdx.x]; // read after the staging barrier
 
     const int64_t cell0 = int64_t(blockIdx.x) * C;
     auto TEN = [&](int i, int c) { return lds + (i * C + c) * CS; };
@@ -185,32 +187,28 @@ __global__ void __launch_bounds__(NT)
         fwd_block(I1{}, I1{}, INQ{}, INP{}, INQ{}, BP, DP, 4);
         fwd_block(I2{}, I2{}, INQ{}, INQ{}, INP{}, BP, DP, 5);
         __syncthreads();
-        // pointwise: v = alpha w kappa M1 V, s = beta w kappa div / |J|, one point at a time
-        // (the six values of a point are read, combined and written back in registers)
-        pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
+        // pointwise: v = alpha w kappa M1 V, s = beta w kappa div / |J|, one point per task
+        // over all threads (the six values of a point are read, combined and written back)
+        for (int t = threadIdx.x; t < C * NQ3; t += NT) {
+            const int c = t / NQ3, q = t - c * NQ3;
+            const int q0 = q / (NQ * NQ), q1 = (q / NQ) % NQ, q2 = q % NQ;
             const int64_t gc = cell0 + c;
-            cptr<T> W = fresh(tW);
-            const T w12 = W[q1] * W[q2];
             T m[6];
 #pragma unroll
-            for (int t = 0; t < 6; ++t) m[t] = T(alpha * sG[c][6 + t]);
+            for (int e = 0; e < 6; ++e) m[e] = T(alpha * sG[c][6 + e]);
             const T sb = T(beta * sG[c][12]);
-            T kq[NQ];
-            ld_coeff(kappa, gc < ncells, gc * NQ3 + q1 * NQ + q2, NQ * NQ, kq);
+            const T kq = (kappa != nullptr && gc < ncells) ? T(to_d(kappa[gc * NQ3 + q])) : T(1);
+            const int o = q0 * S1 + q1 * S2 + q2;
+            const T om = sWq[q0] * sWq[q1] * sWq[q2] * kq;
             T *t0 = TEN(0, c), *t1 = TEN(1, c), *t2 = TEN(2, c), *t3 = TEN(3, c), *t4 = TEN(4, c), *t5 = TEN(5, c);
-#pragma unroll
-            for (int q0 = 0; q0 < NQ; ++q0) {
-                const int o = q0 * S1 + q1 * S2 + q2;
-                const T om = W[q0] * w12 * kq[q0];
-                T x, yv, z;
-                symmv(m, t0[o], t1[o], t2[o], x, yv, z);
-                const T dv = t3[o] + t4[o] + t5[o];
-                t0[o] = om * x;
-                t1[o] = om * yv;
-                t2[o] = om * z;
-                t3[o] = om * sb * dv;
-            }
-        });
+            T x, yv, z;
+            symmv(m, t0[o], t1[o], t2[o], x, yv, z);
+            const T dv = t3[o] + t4[o] + t5[o];
+            t0[o] = om * x;
+            t1[o] = om * yv;
+            t2[o] = om * z;
+            t3[o] = om * sb * dv;
+        }
         __syncthreads();
         // backward B1: axis c, T = BP^T v + DP^T s  (NQ -> NP), in place
         auto bwd_c = [&](auto cblk) {
@@ -283,24 +281,22 @@ __global__ void __launch_bounds__(NT)
             fwd_t(5, I1{}, INQ{}, INP{}, INQ{});
         }
         __syncthreads();
-        // pointwise, one point at a time.  Derivatives present: block 0: d1 V0 (t3), d2 V0 (t6);
+        // pointwise, one point per task over all threads.  Derivatives present: block 0: d1 V0 (t3), d2 V0 (t6);
         // block 1: d0 V1 (t4), d2 V1 (t7); block 2: d0 V2 (t5), d1 V2 (t8).
-        pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
+        for (int t = threadIdx.x; t < C * NQ3; t += NT) {
+            const int c = t / NQ3, q = t - c * NQ3;
+            const int q0 = q / (NQ * NQ), q1 = (q / NQ) % NQ, q2 = q % NQ;
             const int64_t gc = cell0 + c;
-            cptr<T> W = fresh(tW);
-            const T w12 = W[q1] * W[q2];
             T m0[6], m1[6];
 #pragma unroll
-            for (int t = 0; t < 6; ++t) {
-                m0[t] = T(alpha * sG[c][t]);
-                m1[t] = T(beta * sG[c][6 + t]);
+            for (int e = 0; e < 6; ++e) {
+                m0[e] = T(alpha * sG[c][e]);
+                m1[e] = T(beta * sG[c][6 + e]);
             }
-            T kq[NQ];
-            ld_coeff(kappa, gc < ncells, gc * NQ3 + q1 * NQ + q2, NQ * NQ, kq);
-#pragma unroll
-            for (int q0 = 0; q0 < NQ; ++q0) {
+            const T kq = (kappa != nullptr && gc < ncells) ? T(to_d(kappa[gc * NQ3 + q])) : T(1);
+            {
                 const int o = q0 * S1 + q1 * S2 + q2;
-                const T om = W[q0] * w12 * kq[q0];
+                const T om = sWq[q0] * sWq[q1] * sWq[q2] * kq;
                 const T v0 = TEN(0, c)[o], v1 = TEN(1, c)[o], v2 = TEN(2, c)[o];
                 const T d10 = TEN(3, c)[o], d20 = TEN(6, c)[o], d01 = TEN(4, c)[o];
                 const T d21 = TEN(7, c)[o], d02 = TEN(5, c)[o], d12 = TEN(8, c)[o];
@@ -323,7 +319,7 @@ __global__ void __launch_bounds__(NT)
                 TEN(5, c)[o] = -c1; // block 2, d0: r_02 = -c1
                 TEN(8, c)[o] = c0;  // block 2, d1: r_12 =  c0
             }
-        });
+        }
         __syncthreads();
         // backward B1: second P axis o1: V <- BP^T V + DP^T r_o1 ; r_o0 <- BP^T r_o0   (NQ -> NP)
         auto bwd_o1 = [&](auto cblk, auto ax) {
