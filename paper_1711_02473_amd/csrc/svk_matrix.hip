@@ -19,10 +19,10 @@
 // test and trial functions), so the last stage runs four sweeps, not nine.
 //
 // Mapping: one workgroup per (cell, block), one thread per column of the block
-// for p <= 3 (one wave), so that the last stage keeps every lane busy.  The cell's u0 is staged in LDS and its gradient evaluated at
-// each point directly (O(n^6) per block, small
-// beside the O(n^7) matrix stages at these degrees); the block's nine
-// coefficient fields K then stay in LDS for the matrix stages.  Rows of the
+// for p <= 3 (one wave), so that the last stage keeps every lane busy.  The
+// cell's u0 is staged in LDS and its reference gradient sum-factorised (eight
+// one-axis contractions per component); the block's nine coefficient fields K
+// then stay in LDS for the matrix stages.  Rows of the
 // block are written as contiguous (p+1)^3-long runs.
 #include "sf_device.hpp"
 #include "sf_internal.hpp"
@@ -84,6 +84,45 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
         __syncthreads();
     }
 
+    // ---- reference gradient of u0 at the points, sum-factorised one axis at a time:
+    // axis 2 with B and D (sT2: [c][B|D][i0][i1][q2]); axis 1 (sT1: [c][BB|DB|BD][i0][q1][q2],
+    // the first letter the axis-1 table); axis 0 into sK ([c][d][q]: d0 = D0 BB, d1 = B0 DB,
+    // d2 = B0 BD).  The pointwise stage below reads a point's nine values and then
+    // overwrites the same point of sK with the coefficients.
+    for (int t = tid; t < 6 * N3; t += NT) {
+        const int cs = t / N3, r = t - cs * N3, c = cs >> 1;
+        const int i01 = r / N, q2 = r - i01 * N;
+        const double *X = (cs & 1) ? sD : sB;
+        const double *uc = sU + c * N3 + i01 * N;
+        double acc = 0.0;
+#pragma unroll
+        for (int i2 = 0; i2 < N; ++i2) acc = fma(X[q2 * N + i2], uc[i2], acc);
+        sT2[t] = acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < 9 * N3; t += NT) {
+        const int ck = t / N3, r = t - ck * N3, c = ck / 3, k = ck - c * 3;
+        const int i0 = r / N2, q1 = (r / N) % N, q2 = r % N;
+        const double *X = k == 1 ? sD : sB;                                   // axis-1 table
+        const double *src = sT2 + (2 * c + (k == 2 ? 1 : 0)) * N3 + i0 * N2 + q2; // B or D on axis 2
+        double acc = 0.0;
+#pragma unroll
+        for (int i1 = 0; i1 < N; ++i1) acc = fma(X[q1 * N + i1], src[i1 * N], acc);
+        sT1[t] = acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < 9 * N3; t += NT) {
+        const int cd = t / N3, q = t - cd * N3, c = cd / 3, d = cd - c * 3;
+        const int q0 = q / N2, q12 = q - q0 * N2;
+        const double *X = d == 0 ? sD : sB; // axis-0 table
+        const double *src = sT1 + (3 * c + d) * N3 + q12;
+        double acc = 0.0;
+#pragma unroll
+        for (int i0 = 0; i0 < N; ++i0) acc = fma(X[q0 * N + i0], src[i0 * N2], acc);
+        sK[t] = acc;
+    }
+    __syncthreads();
+
     // ---- coefficient fields of this block at every point
     for (int q = tid; q < N3; q += NT) {
         const int q0 = q / N2, q1 = (q / N) % N, q2 = q % N;
@@ -102,27 +141,11 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
             wdet = sGeo[33];
         }
         wdet *= sW[q0] * sW[q1] * sW[q2];
-        // reference gradient of u0 at q, directly: gu[c][d] = sum_i u_c[i] X^d_i(q)
-        double gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        for (int i0 = 0; i0 < N; ++i0) {
-            const double b0 = sB[q0 * N + i0], d0 = sD[q0 * N + i0];
-            for (int i1 = 0; i1 < N; ++i1) {
-                const double b1 = sB[q1 * N + i1], d1 = sD[q1 * N + i1];
+        double gu[3][3]; // reference gradient of u0 at q
 #pragma unroll
-                for (int i2 = 0; i2 < N; ++i2) {
-                    const double b2 = sB[q2 * N + i2], d2 = sD[q2 * N + i2];
-                    const double x0 = d0 * b1 * b2, x1 = b0 * d1 * b2, x2 = b0 * b1 * d2;
-                    const int i = (i0 * N + i1) * N + i2;
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double uv = sU[c * N3 + i];
-                        gu[c][0] = fma(uv, x0, gu[c][0]);
-                        gu[c][1] = fma(uv, x1, gu[c][1]);
-                        gu[c][2] = fma(uv, x2, gu[c][2]);
-                    }
-                }
-            }
-        }
+            for (int d = 0; d < 3; ++d) gu[c][d] = sK[(3 * c + d) * N3 + q];
         double F[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
