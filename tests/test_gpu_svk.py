@@ -139,3 +139,20 @@ def test_svk_element_matrix_limits(ctxs):
         A = empty((2, nd, nd), np.float64)
         with pytest.raises(sf.SfError):
             sf.assemble_element_matrix(ctxs["affine"], op, 2, dev(V), None, A)
+
+
+def test_svk_element_matrix_at_rest_and_empty(ctxs):
+    """u0 = NULL is the linearisation at rest (linear elasticity); ncells = 0 is a no-op."""
+    p, n = 2, 4
+    V = synth.affine_cells(n, 170)
+    nd = 3 * (p + 1) ** 3
+    op = sf.make_op("Q", p, "SVK", alpha=LAM, beta=MU)
+    A = empty((n, nd, nd), np.float64)
+    sf.assemble_element_matrix(ctxs["affine"], op, n, dev(V), None, A)
+    assert sf.sf_check_errors(ctxs["affine"]) == 0
+    ref = oracle.svk_matrix("Q", p, V, np.zeros((n, nd)), LAM, MU)
+    assert rel_l2(host(A), ref) <= 1e-12
+    y = empty((1, nd), np.float64)
+    sf.assemble_action(ctxs["affine"], op, 0, dev(V), None, dev(np.zeros((1, nd))), y)
+    sf.assemble_element_matrix(ctxs["affine"], op, 0, dev(V), None, A)
+    assert sf.sf_check_errors(ctxs["affine"]) == 0
