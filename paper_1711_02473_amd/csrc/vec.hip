@@ -75,7 +75,7 @@ template <typename T> __device__ __forceinline__ void symmv(const T m[6], T a, T
 // action
 // ---------------------------------------------------------------------------
 template <int FAM, int K, typename T, typename IO, int C, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8)))
     action_vec_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                       const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab, int *__restrict__ err,
                       const double alpha, const double beta)
