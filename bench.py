@@ -226,13 +226,15 @@ def main():
 
 
 def source_digest():
-    """SHA-256 over the library's kernel and interface sources (sorted by path):
-    identifies the kernels a recorded profile was taken from."""
+    """SHA-256 over the library's kernel and interface sources (sorted by path; build
+    intermediates beside them are not counted): identifies the kernels a recorded
+    profile was taken from."""
     import glob
     import hashlib
 
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1711_02473_amd", "csrc", "*.*"))) + \
+    csrc = os.path.join(ROOT, "paper_1711_02473_amd", "csrc")
+    files = sorted(f for ext in ("hip", "inc", "hpp", "cpp") for f in glob.glob(os.path.join(csrc, "*." + ext))) + \
         [os.path.join(ROOT, "include", "sf.h")]
     for f in files:
         h.update(os.path.relpath(f, ROOT).encode())

@@ -27,7 +27,7 @@
 namespace sf {
 
 template <int N, int NQ, int FORM, bool COLL, int MODE, typename IO, int C, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     action_mixed_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                         const IO *__restrict__ u, IO *__restrict__ y, const double *__restrict__ tab64,
                         const uint16_t *__restrict__ mix, int *__restrict__ err)
@@ -45,7 +45,9 @@ int launch_one(const LaunchArgs &a)
     constexpr int NQ = N;
     constexpr int NBUF = (FORM == SF_LAPLACE) ? 4 : 1;
     constexpr int CS = Lds3<NQ>::CS;
-    constexpr int C0 = (40 * 1024) / (NBUF * CS * 4);
+    // as many cells as keep the whole LDS footprint (tensors, per-cell factors, weights)
+    // within 40 KiB, so that four workgroups fit in a CU's 160 KiB
+    constexpr int C0 = (40 * 1024 - 4 * (NQ + 64) - 8) / (NBUF * CS * 4 + 8 * 6);
     constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);
     constexpr int NT = 256;
     const int64_t groups = (a.ncells + C - 1) / C;
