@@ -27,10 +27,13 @@
 
 namespace sf {
 
+// Register target of five waves per SIMD (80 VGPRs, no spills): more resident workgroups
+// hide the write latency; measured faster for p = 1 and 3, slower for p = 2 (kept at the
+// compiler's default there), no effect for p >= 4.
 template <int N, int NQ, int FORM, typename IO, int C, int NT, int R>
-__global__ void __launch_bounds__(NT) matrix_q_kernel(const int64_t ncells, const double *__restrict__ vert,
-                                                      const IO *__restrict__ kappa, IO *__restrict__ A,
-                                                      const double *__restrict__ tab, int *__restrict__ err)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(N == 3 ? 1 : 5, 8)))
+    matrix_q_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
+                    IO *__restrict__ A, const double *__restrict__ tab, int *__restrict__ err)
 {
     __shared__ double smem[MatrixQSmem<N, NQ, FORM, C>::doubles];
     matrix_q_body<N, NQ, FORM, IO, C, NT, R>(int64_t(blockIdx.x) * C, ncells, vert, kappa, A, 0, tab, err, smem);
