@@ -26,11 +26,14 @@
 namespace sf {
 
 
+// Trilinear Laplace at p = 6: a register target of three waves per SIMD (the LDS limit;
+// 168 VGPRs, a few spilled) measured 10 % faster than the compiler's two; the same at p = 4
+// (four waves) and p = 8 spilled too much and was slower.
 template <int N, int NQ, int FORM, bool COLL, typename T, typename IO, int C, int NT, bool TRI>
-__global__ void __launch_bounds__(NT) action_q_kernel(const int64_t ncells, const double *__restrict__ vert,
-                                                      const IO *__restrict__ kappa, const IO *__restrict__ u,
-                                                      IO *__restrict__ y, const T *__restrict__ tab,
-                                                      int *__restrict__ err)
+__global__ void __launch_bounds__(NT)
+    __attribute__((amdgpu_waves_per_eu(TRI && FORM == SF_LAPLACE && N == 7 ? 3 : 1, 8)))
+    action_q_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
+                    const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab, int *__restrict__ err)
 {
     __shared__ double smem[ActionQSmem<N, NQ, FORM, COLL, T, C>::bytes / 8];
     action_q_body<N, NQ, FORM, COLL, T, IO, C, NT, TRI>(int64_t(blockIdx.x) * C, ncells, vert, kappa, u, y, tab,
