@@ -13,6 +13,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sf_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
+# a separately built copy (e.g. an AddressSanitizer / UBSan build made by the
+# sanitizer test) may be named here; it is loaded as is, never rebuilt
+_LIB_OVERRIDE = os.environ.get("SF_ORACLE_LIB", "")
 
 FAMILIES = {"Q": 0, "DQ": 1, "NCF": 2, "NCE": 3, "QGLL": 4, "VQ": 5}
 FORMS = {"MASS": 0, "LAPLACE": 1, "HDIV": 2, "HCURL": 3}
@@ -36,9 +39,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    if _LIB_OVERRIDE:
+        lib = ctypes.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     lib.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]

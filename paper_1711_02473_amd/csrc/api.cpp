@@ -371,13 +371,17 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     if (ncells == 0) return SF_OK;
     if (!vertices || !u || !y) return SF_ERR_ARG;
     if (y == u || y == kappa) return SF_ERR_ARG;
+    // checks that need no device state come before make_args (which may allocate tables)
+    if (op->form == SF_SVK_RESIDUAL && kappa) return SF_ERR_ARG;
+    if (ctx->geometry == SF_GEOM_TRILINEAR && scalar_family(op->family) &&
+        (op->precision != SF_FP64 || op->io_dtype != SF_F64))
+        return SF_ERR_UNSUPPORTED; // per-point geometry is built for FP64 contractions and storage
     LaunchArgs a;
     rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
     if (rc) return rc;
     a.u = u;
     a.y = y;
     if (svk_form(op->form) || op->family == SF_VQ) {
-        if (op->form == SF_SVK_RESIDUAL && kappa) return SF_ERR_ARG;
         a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
         return launch_action_vq(a);
     }
