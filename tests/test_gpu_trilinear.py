@@ -30,9 +30,9 @@ def launch(ctx, op, V, kap, u):
 
 @pytest.mark.parametrize("family", ["Q", "DQ", "QGLL"])
 @pytest.mark.parametrize("form", ["LAPLACE", "MASS"])
-@pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
+@pytest.mark.parametrize("p", range(1, 9))
 def test_trilinear_action(ctx, family, form, p):
-    n = {1: 150, 2: 90, 4: 25, 6: 9, 8: 4}[p]
+    n = {1: 150, 2: 90, 3: 41, 4: 25, 5: 14, 6: 9, 7: 6, 8: 4}[p]
     V = synth.trilinear_cells(n, 30 + p)
     nq = (p + 1) ** 3
     kap = synth.kappa(n, nq, 30 + p)
@@ -60,6 +60,35 @@ def test_trilinear_mode_flags_inverted_points_and_rejects_low_precision(ctx):
     u = synth.dof_vector(6, 27, 32)
     _, f = launch(ctx, sf.make_op("Q", 2, "LAPLACE"), V, None, u)
     assert f & sf.SF_FLAG_DETJ
-    with pytest.raises(sf.SfError):
-        launch(ctx, sf.make_op("Q", 2, "LAPLACE", precision="fp32"), synth.trilinear_cells(2, 33), None,
-               synth.dof_vector(2, 27, 33))
+    for prec, io in (("fp32", "f64"), ("fp64", "f32"), ("bf16", "f64"), ("fp16", "f64"), ("bf16x3", "f64"),
+                     ("bf16x3", "f32")):
+        with pytest.raises(sf.SfError) as e:
+            op = sf.make_op("Q", 2, "LAPLACE", precision=prec, io=io)
+            nd, _ = sf.sf_element_dims(op)
+            npio = np.float32 if io == "f32" else np.float64
+            y = empty((2, nd), npio)
+            sf.assemble_action(ctx, op, 2, dev(synth.trilinear_cells(2, 33)), None,
+                               dev(synth.dof_vector(2, 27, 33).astype(npio)), y)
+        assert e.value.code == sf.SF_ERR_UNSUPPORTED, (prec, io)
+
+
+@pytest.mark.parametrize("p", [3, 7])
+def test_trilinear_full_size_sampled(ctx, p):
+    """The benchmark's trilinear workload in its launch configuration: 64^3 perturbed
+    cells, kappa and u drawn on the GPU as the benchmark draws them; sampled cells
+    (first, last, spread) checked against the oracle cell by cell, every output finite."""
+    import torch
+    n = 64 ** 3
+    nd = (p + 1) ** 3
+    Vh = synth.trilinear_cells(n, 7)
+    (kap, u), = synth.device_action_inputs(n, nd, 2, p)
+    y = torch.empty_like(u)
+    y.fill_(np.nan)
+    print("case trilinear full-size p", p, flush=True)
+    sf.assemble_action(ctx, sf.make_op("Q", p, "LAPLACE"), n, dev(Vh), kap, u, y)
+    assert sf.sf_check_errors(ctx) == 0
+    idx = np.unique(np.concatenate([np.linspace(0, n - 1, 48).astype(np.int64), [n - 1, n - 2]]))
+    ti = torch.from_numpy(idx).cuda()
+    ref = oracle.action("Q", p, "LAPLACE", Vh[idx], host(u[ti]), kappa=host(kap[ti]))
+    assert rel_l2(host(y[ti]), ref) <= 1e-12
+    assert bool(torch.isfinite(y).all())

@@ -97,17 +97,43 @@ def test_element_matrix_mass_and_action_consistency(ctx, family, k):
 
 
 @pytest.mark.parametrize("family", ["NCF", "NCE"])
-@pytest.mark.parametrize("prec,io,tol", [("fp32", "f32", 5e-6), ("fp64", "f32", 2e-6)])
-def test_action_fp32(ctx, family, prec, io, tol):
-    k = 4
-    V = synth.box_mesh(2, 2, 5, 80)
-    nd = oracle.ndof(family, k)
-    u = synth.dof_vector(len(V), nd, 80)
+@pytest.mark.parametrize("k", range(1, 7))
+@pytest.mark.parametrize("prec,io,tol", [("fp32", "f32", 5e-6), ("fp64", "f32", 2e-6), ("fp32", "f64", 5e-6)])
+def test_action_fp32(ctx, family, k, prec, io, tol):
+    """FP32 contractions and/or FP32 storage at every degree the benchmark times, on
+    boxes (a ragged cell count) and on sheared cells; the oracle runs on the FP32-rounded
+    inputs, so the error is the kernels' own."""
+    grid = (3, 3, 5) if k <= 3 else (2, 3, 4)
     npio = np.float32 if io == "f32" else np.float64
-    y, flags = gpu_action(ctx, sf.make_op(family, k, FORM[family], precision=prec, io=io), V, None, u, io=npio)
-    ref = oracle.action(family, k, FORM[family], V, u.astype(npio).astype(np.float64))
-    assert flags == 0
-    assert rel_l2(y, ref) <= tol
+    op = sf.make_op(family, k, FORM[family], precision=prec, io=io, alpha=1.2, beta=0.8)
+    nd = oracle.ndof(family, k)
+    for V in (synth.box_mesh(*grid, 80 + k)[:-1], synth.affine_cells(7, 81 + k)):
+        u = synth.dof_vector(len(V), nd, 80 + k)
+        y, flags = gpu_action(ctx, op, V, None, u, io=npio)
+        ref = oracle.action(family, k, FORM[family], V, u.astype(npio).astype(np.float64), alpha=1.2, beta=0.8)
+        assert flags == 0
+        assert rel_l2(y, ref) <= tol, rel_l2(y, ref)
+
+
+@pytest.mark.parametrize("family", ["NCF", "NCE"])
+@pytest.mark.parametrize("k", [1, 3, 6])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_48cubed_f32_storage_sampled(ctx, family, k, prec):
+    """The 48^3 workload with FP32 storage (the benchmark's FP32 rows), in its launch
+    configuration: sampled cells against the oracle run on the FP32-rounded inputs."""
+    V = synth.box_mesh(48, 48, 48, 4)
+    n = len(V)
+    nd = oracle.ndof(family, k)
+    u = synth.dof_vector(n, nd, 4).astype(np.float32)
+    dy = empty((n, nd), np.float32)
+    dy.fill_(np.nan)
+    sf.assemble_action(ctx, sf.make_op(family, k, FORM[family], precision=prec, io="f32"), n, dev(V), None, dev(u), dy)
+    assert sf.sf_check_errors(ctx) == 0
+    y = host(dy)
+    assert np.isfinite(y).all()
+    idx = np.unique(np.concatenate([np.linspace(0, n - 1, 40).astype(np.int64), [n - 1]]))
+    ref = oracle.action(family, k, FORM[family], V[idx], u[idx].astype(np.float64))
+    assert rel_l2(y[idx], ref) <= (2e-6 if prec == "fp64" else 5e-6)
 
 
 @pytest.mark.parametrize("family", ["NCF", "NCE"])
