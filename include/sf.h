@@ -18,8 +18,8 @@
  *     kernels take AFFINE cells (x = x0 + J xi, which includes axis-aligned
  *     boxes); a cell whose remaining vertices deviate from the affine map, or
  *     whose det J <= 0, raises a device-side flag read by sf_check_errors()
- *     and its output is unspecified.  Element matrices additionally require
- *     axis-aligned boxes (diagonal J) and flag other cells the same way.
+ *     and its output is unspecified.  sf_set_geometry() declares boxes
+ *     (faster kernels) or general trilinear cells (geometry per point).
  *   - Quadrature: nq1 Gauss-Legendre points per axis (Gauss-Lobatto-Legendre
  *     for SF_QGLL) (tensor rule, eq. tpps),
  *     point q = (q0*nq1 + q1)*nq1 + q2.  kappa, when given, is a value per
@@ -152,9 +152,9 @@ const char *sf_status_string(int status);
  * unspecified and raises SF_FLAG_NONBOX, except when the autotuner picked
  * the general kernel for that op (variant 3 below), which stays exact and
  * raises nothing; the mass action needs only |det J| and stays exact on any
- * affine cell.  The hint does not change
- * element matrices or the H(div) / H(curl) kernels.  Returns SF_ERR_ARG for
- * an unknown value. */
+ * affine cell.  Element matrices of SF_Q / SF_VQ then use the box kernel
+ * (see assemble_element_matrix); the H(div) / H(curl) kernels do not change.
+ * Returns SF_ERR_ARG for an unknown value. */
 #define SF_GEOM_AFFINE 0
 #define SF_GEOM_BOX 1
 /* SF_GEOM_TRILINEAR: cells may be general trilinear hexahedra (the vector-Q1
@@ -162,8 +162,11 @@ const char *sf_status_string(int status);
  * J, |J| and |J| G G^T at every quadrature point (the per-point factor
  * P^{(k,l)}_q of Sec. 3.2, all six entries) in FP64 and need SF_FP64 with
  * SF_F64 storage (else SF_ERR_UNSUPPORTED); a point with det J <= 0 raises
- * SF_FLAG_DETJ.  Element matrices, the H(div) / H(curl) kernels and the
- * lower-precision actions keep their affine / box requirements. */
+ * SF_FLAG_DETJ.  The same holds for the SF_NCF / SF_NCE actions (Piola
+ * factors J^T J / |J|, |J| G G^T and 1 / |J| per point), the vector and
+ * hyperelastic forms and the scalar element matrices; every action under
+ * this hint needs SF_FP64 contractions with SF_F64 storage.  The SF_NCF /
+ * SF_NCE element matrices keep the box requirement. */
 #define SF_GEOM_TRILINEAR 2
 int sf_set_geometry(sf_context *ctx, int32_t geometry);
 
@@ -218,9 +221,20 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
  * contraction merged by distributivity, Sec. 3.6 pass 6):
  *   A[c][i][j] = a(psi_j, psi_i) on cell c, row i = test, column j = trial,
  *   device [ncells][ndof_cell][ndof_cell] io_dtype, overwritten.
- * Other arguments and errors as assemble_action().  Cells must be
- * axis-aligned boxes, except for SF_SVK (affine or, under
- * SF_GEOM_TRILINEAR, trilinear cells).
+ * Other arguments and errors as assemble_action().  FP64 contractions
+ * (SF_ERR_UNSUPPORTED otherwise).  Geometry, by the context's hint:
+ *   SF_Q, SF_VQ: SF_GEOM_BOX: axis-aligned boxes, the three diagonal
+ *     products (a sheared cell raises SF_FLAG_NONBOX); SF_GEOM_AFFINE (the
+ *     default): any affine cell, all nine products P^{(a,b)} of eq.
+ *     poisson_gem with the symmetric factor |J| G G^T; SF_GEOM_TRILINEAR:
+ *     trilinear cells, the same nine products with J, G and |J| at every
+ *     point.
+ *   SF_QGLL, SF_DQ (quadrature points = nodes, B = I, Sec. 2.5): every
+ *     geometry as above, assembled from the O(n^5) structured nonzeros
+ *     (delta cancellation of the identity factors); the mass matrix is
+ *     diagonal.
+ *   SF_NCF, SF_NCE: axis-aligned boxes (others raise SF_FLAG_NONBOX).
+ *   SF_SVK: affine cells or, under SF_GEOM_TRILINEAR, trilinear cells.
  */
 int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
                             const void *kappa, void *A, void *hip_stream);

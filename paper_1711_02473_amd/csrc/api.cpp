@@ -142,6 +142,51 @@ bool pack_eo(std::vector<double> &h, int src, int dst, int n, bool skew)
     return true;
 }
 
+} // namespace
+
+namespace sf {
+// The FP64 table block of one (family, degree, nq1) in the TabLayout order
+// (host only, no device state).  Returns SF_OK or SF_ERR_UNSUPPORTED.
+int host_table_block(int family, int n0, int n1, int nq1, std::vector<double> &h)
+{
+    TabLayout L(n0, n1, nq1);
+    h.assign(L.size(), 0.0);
+    std::vector<double> xq(nq1), wq(nq1), x0(n0), w0(n0), x1(std::max(n1, 1)), w1(std::max(n1, 1));
+    // quadrature: GL, or GLL for the collocated variant (nodes = points, B = I)
+    rule_1d(family == SF_QGLL ? 1 : 0, nq1, xq.data(), wq.data());
+    if (family == SF_DQ) rule_1d(0, n0, x0.data(), w0.data());
+    else rule_1d(1, n0, x0.data(), w0.data()); // Q_p and the P_k factor: GLL nodes
+    lagrange_table(n0, x0.data(), nq1, xq.data(), h.data() + L.B0(), h.data() + L.D0());
+    if (n1 > 0) {
+        rule_1d(0, n1, x1.data(), w1.data()); // dP_{k-1}: GL nodes
+        lagrange_table(n1, x1.data(), nq1, xq.data(), h.data() + L.B1(), h.data() + L.D1());
+    }
+    std::vector<double> tmpB(size_t(nq1) * nq1);
+    lagrange_table(nq1, xq.data(), nq1, xq.data(), tmpB.data(), h.data() + L.Dh());
+    std::copy(wq.begin(), wq.end(), h.begin() + L.W());
+    std::copy(xq.begin(), xq.end(), h.begin() + L.XQ());
+    auto transpose = [&](int src, int dst, int rows, int cols) {
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) h[dst + size_t(c) * rows + r] = h[src + size_t(r) * cols + c];
+    };
+    transpose(L.B0(), L.B0T(), nq1, n0);
+    transpose(L.D0(), L.D0T(), nq1, n0);
+    transpose(L.B1(), L.B1T(), nq1, n1);
+    transpose(L.D1(), L.D1T(), nq1, n1);
+    transpose(L.Dh(), L.DhT(), nq1, nq1);
+    if (n0 == nq1) {
+        // node and point sets are symmetric about 1/2, so B and B^T are centrosymmetric and
+        // Dh, Dh^T skew-centrosymmetric; pack their even-odd forms (see apply_eo)
+        const bool ok = pack_eo(h, L.B0(), L.BEO(), nq1, false) && pack_eo(h, L.B0T(), L.BTEO(), nq1, false) &&
+                        pack_eo(h, L.Dh(), L.DhEO(), nq1, true) && pack_eo(h, L.DhT(), L.DhTEO(), nq1, true);
+        if (!ok) return SF_ERR_UNSUPPORTED;
+    }
+    return SF_OK;
+}
+} // namespace sf
+
+namespace {
+
 int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out)
 {
     auto key = std::make_tuple(int(op->family), int(op->degree), d.nq1);
@@ -151,37 +196,9 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
         return SF_OK;
     }
     TabLayout L(d.n0, d.n1, d.nq1);
-    std::vector<double> h(L.size(), 0.0);
-    std::vector<double> xq(d.nq1), wq(d.nq1), n0(d.n0), w0(d.n0), n1(std::max(d.n1, 1)), w1(std::max(d.n1, 1));
-    // quadrature: GL, or GLL for the collocated variant (nodes = points, B = I)
-    rule_1d(op->family == SF_QGLL ? 1 : 0, d.nq1, xq.data(), wq.data());
-    if (op->family == SF_DQ) rule_1d(0, d.n0, n0.data(), w0.data());
-    else rule_1d(1, d.n0, n0.data(), w0.data()); // Q_p and the P_k factor: GLL nodes
-    lagrange_table(d.n0, n0.data(), d.nq1, xq.data(), h.data() + L.B0(), h.data() + L.D0());
-    if (d.n1 > 0) {
-        rule_1d(0, d.n1, n1.data(), w1.data()); // dP_{k-1}: GL nodes
-        lagrange_table(d.n1, n1.data(), d.nq1, xq.data(), h.data() + L.B1(), h.data() + L.D1());
-    }
-    std::vector<double> tmpB(size_t(d.nq1) * d.nq1);
-    lagrange_table(d.nq1, xq.data(), d.nq1, xq.data(), tmpB.data(), h.data() + L.Dh());
-    std::copy(wq.begin(), wq.end(), h.begin() + L.W());
-    std::copy(xq.begin(), xq.end(), h.begin() + L.XQ());
-    auto transpose = [&](int src, int dst, int rows, int cols) {
-        for (int r = 0; r < rows; ++r)
-            for (int c = 0; c < cols; ++c) h[dst + size_t(c) * rows + r] = h[src + size_t(r) * cols + c];
-    };
-    transpose(L.B0(), L.B0T(), d.nq1, d.n0);
-    transpose(L.D0(), L.D0T(), d.nq1, d.n0);
-    transpose(L.B1(), L.B1T(), d.nq1, d.n1);
-    transpose(L.D1(), L.D1T(), d.nq1, d.n1);
-    transpose(L.Dh(), L.DhT(), d.nq1, d.nq1);
-    if (d.n0 == d.nq1) {
-        // node and point sets are symmetric about 1/2, so B and B^T are centrosymmetric and
-        // Dh, Dh^T skew-centrosymmetric; pack their even-odd forms (see apply_eo)
-        const bool ok = pack_eo(h, L.B0(), L.BEO(), d.nq1, false) && pack_eo(h, L.B0T(), L.BTEO(), d.nq1, false) &&
-                        pack_eo(h, L.Dh(), L.DhEO(), d.nq1, true) && pack_eo(h, L.DhT(), L.DhTEO(), d.nq1, true);
-        if (!ok) return SF_ERR_UNSUPPORTED;
-    }
+    std::vector<double> h;
+    const int hrc = host_table_block(op->family, d.n0, d.n1, d.nq1, h);
+    if (hrc) return hrc;
 
     TableSet ts;
     ts.len = L.size();
@@ -373,8 +390,7 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     if (y == u || y == kappa) return SF_ERR_ARG;
     // checks that need no device state come before make_args (which may allocate tables)
     if (op->form == SF_SVK_RESIDUAL && kappa) return SF_ERR_ARG;
-    if (ctx->geometry == SF_GEOM_TRILINEAR && scalar_family(op->family) &&
-        (op->precision != SF_FP64 || op->io_dtype != SF_F64))
+    if (ctx->geometry == SF_GEOM_TRILINEAR && (op->precision != SF_FP64 || op->io_dtype != SF_F64))
         return SF_ERR_UNSUPPORTED; // per-point geometry is built for FP64 contractions and storage
     LaunchArgs a;
     rc = make_args(ctx, op, ncells, vertices, kappa, hip_stream, a, d);
@@ -400,6 +416,7 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
         }
         return launch_action_q(a);
     }
+    a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
     return launch_action_vec(a);
 }
 
@@ -446,7 +463,11 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
         a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
         return launch_matrix_svk(a);
     }
-    if (scalar_family(op->family) || op->family == SF_VQ) return launch_matrix_q(a);
+    a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
+    // collocated families (points = nodes, B = I): the O(n^5) structured assembly, any geometry
+    if (op->family == SF_QGLL || op->family == SF_DQ) return launch_matrix_coll(a);
+    if (scalar_family(op->family) || op->family == SF_VQ)
+        return ctx->geometry == SF_GEOM_BOX ? launch_matrix_q(a) : launch_matrix_qgen(a);
     return launch_matrix_vec(a);
 }
 

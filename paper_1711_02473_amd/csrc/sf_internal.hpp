@@ -101,10 +101,15 @@ int launch_matrix_svk(const LaunchArgs &a);
 int launch_action_q_fast(const LaunchArgs &a);
 int launch_action_q_global(const LaunchArgs &a, int nx, int ny, int nz);
 int launch_matrix_q(const LaunchArgs &a);
+int launch_matrix_qgen(const LaunchArgs &a);
+int launch_matrix_coll(const LaunchArgs &a);
 int launch_action_vec(const LaunchArgs &a);
 int launch_matrix_vec(const LaunchArgs &a);
 int launch_action_mixed(const LaunchArgs &a);
 int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);
+
+// host-side table block of one element (TabLayout order, FP64)
+int host_table_block(int family, int n0, int n1, int nq1, std::vector<double> &h);
 
 // tuning keys: what = "batch" (cell groups per tile) or "standalone" (kernel variant)
 std::string tune_key(const sf_op *op, const char *what);

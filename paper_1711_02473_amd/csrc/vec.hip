@@ -1,6 +1,7 @@
 // H(div) (NCF, "RTCF" on hexahedra) and H(curl) (NCE) elements of the Q^-
-// family on gfx950: operator action (any affine cell) and element matrices
-// (axis-aligned boxes), FP64 or FP32 contractions.
+// family on gfx950: operator action (any affine cell, FP64 or FP32
+// contractions; general trilinear cells with FP64 contractions and storage)
+// and element matrices (axis-aligned boxes).
 //
 // Method.  The element is an enriched element of three tensor-product blocks
 // (Sec. 2.6-2.7, eq. rtcf_impl); splitting the Concatenate node together with
@@ -62,6 +63,26 @@ __device__ inline int vec_geometry(const double *X, double M0[6], double M1[6], 
     return f;
 }
 
+// the same factors at one point of a trilinear cell (J from the eight vertices at
+// reference point (x0, x1, x2)); returns det J
+__device__ inline double vec_point_geometry(const double *X, double x0, double x1, double x2, double M0[6],
+                                            double M1[6], double &rS)
+{
+    double J[3][3];
+    const double det = trilinear_jacobian(X, x0, x1, x2, J);
+    const double S = fabs(det);
+    rS = S > 0.0 ? 1.0 / S : 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) M0[t] = 0.0;
+    if (det != 0.0) laplace_factor(J, det, M0);
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = k; l < 3; ++l) M1[t++] = (J[0][k] * J[0][l] + J[1][k] * J[1][l] + J[2][k] * J[2][l]) * rS;
+    return det;
+}
+
 template <typename T> __device__ __forceinline__ void symmv(const T m[6], T a, T b, T c, T &x, T &y, T &z)
 {
     x = m[0] * a + m[1] * b + m[2] * c;
@@ -74,7 +95,9 @@ template <typename T> __device__ __forceinline__ void symmv(const T m[6], T a, T
 // ---------------------------------------------------------------------------
 // action
 // ---------------------------------------------------------------------------
-template <int FAM, int K, typename T, typename IO, int C, int NT>
+// TRI: general trilinear cells, the Piola factors evaluated at every point from the
+// eight vertices (J per point, Sec. 3.1) instead of once per affine cell
+template <int FAM, int K, typename T, typename IO, int C, int NT, bool TRI = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8)))
     action_vec_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                       const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab, int *__restrict__ err,
@@ -102,6 +125,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8)))
     __shared__ T lds[NTEN * C * CS];
     __shared__ double sG[C][13];
     __shared__ T sWq[NQ]; // 1-D weights (lane-dependent reads in the pointwise stage)
+    __shared__ double sXq[TRI ? NQ : 1], sVx[TRI ? C : 1][24]; // points and vertices (trilinear cells)
+    static_assert(!TRI || std::is_same<T, double>::value, "trilinear cells: FP64 contractions");
     if (threadIdx.x < NQ) sWq[threadIdx.x] = tW[threadIdx.x]; // read after the staging barrier
 
     const int64_t cell0 = int64_t(blockIdx.x) * C;
@@ -111,7 +136,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8)))
     T uv[KU];
     ld_rows<C, NF, NT>(u, cell0, ncells, T(0), uv);
 
-    if (threadIdx.x < C) {
+    if constexpr (TRI) {
+        // the points (FP64 table block) and the group's vertices, for the per-point factors
+        if (threadIdx.x < NQ) sXq[threadIdx.x] = reinterpret_cast<const double *>(tab)[TL.XQ() + threadIdx.x];
+        for (int t = threadIdx.x; t < 24 * C; t += NT)
+            sVx[t / 24][t % 24] = cell0 + t / 24 < ncells ? vert[cell0 * 24 + t] : 0.0;
+    } else if (threadIdx.x < C) {
         const int64_t gc = cell0 + threadIdx.x;
         double M0[6] = {0, 0, 0, 0, 0, 0}, M1[6] = {0, 0, 0, 0, 0, 0}, rS = 0.0;
         if (gc < ncells) {
@@ -193,10 +223,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8)))
             const int c = t / NQ3, q = t - c * NQ3;
             const int q0 = q / (NQ * NQ), q1 = (q / NQ) % NQ, q2 = q % NQ;
             const int64_t gc = cell0 + c;
-            T m[6];
+            T m[6], sb;
+            if constexpr (TRI) {
+                double M0[6], M1[6], rS;
+                const double det = vec_point_geometry(sVx[c], sXq[q0], sXq[q1], sXq[q2], M0, M1, rS);
+                if (!(det > 0.0) && gc < ncells) atomicOr(err, SF_FLAG_DETJ);
 #pragma unroll
-            for (int e = 0; e < 6; ++e) m[e] = T(alpha * sG[c][6 + e]);
-            const T sb = T(beta * sG[c][12]);
+                for (int e = 0; e < 6; ++e) m[e] = T(alpha * M1[e]);
+                sb = T(beta * rS);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) m[e] = T(alpha * sG[c][6 + e]);
+                sb = T(beta * sG[c][12]);
+            }
             const T kq = (kappa != nullptr && gc < ncells) ? T(to_d(kappa[gc * NQ3 + q])) : T(1);
             const int o = q0 * S1 + q1 * S2 + q2;
             const T om = sWq[q0] * sWq[q1] * sWq[q2] * kq;
@@ -288,10 +327,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8)))
             const int q0 = q / (NQ * NQ), q1 = (q / NQ) % NQ, q2 = q % NQ;
             const int64_t gc = cell0 + c;
             T m0[6], m1[6];
+            if constexpr (TRI) {
+                double M0[6], M1[6], rS;
+                const double det = vec_point_geometry(sVx[c], sXq[q0], sXq[q1], sXq[q2], M0, M1, rS);
+                if (!(det > 0.0) && gc < ncells) atomicOr(err, SF_FLAG_DETJ);
 #pragma unroll
-            for (int e = 0; e < 6; ++e) {
-                m0[e] = T(alpha * sG[c][e]);
-                m1[e] = T(beta * sG[c][6 + e]);
+                for (int e = 0; e < 6; ++e) {
+                    m0[e] = T(alpha * M0[e]);
+                    m1[e] = T(beta * M1[e]);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    m0[e] = T(alpha * sG[c][e]);
+                    m1[e] = T(beta * sG[c][6 + e]);
+                }
             }
             const T kq = (kappa != nullptr && gc < ncells) ? T(to_d(kappa[gc * NQ3 + q])) : T(1);
             {
@@ -565,7 +615,7 @@ __global__ void __launch_bounds__(NT)
 
 namespace {
 
-template <int FAM, int K, typename T, typename IO>
+template <int FAM, int K, typename T, typename IO, bool TRI = false>
 int launch_action_one(const LaunchArgs &a, const T *tab)
 {
     // one or two waves per block, C cells so that a block's n^2 pencils fill them
@@ -577,7 +627,7 @@ int launch_action_one(const LaunchArgs &a, const T *tab)
     if (groups > 0x7fffffffLL) return SF_ERR_CAPACITY;
     const double al = (a.form == SF_MASS) ? 1.0 : a.alpha;
     const double be = (a.form == SF_MASS) ? 0.0 : a.beta;
-    hipLaunchKernelGGL((action_vec_kernel<FAM, K, T, IO, C, NT>), dim3(unsigned(groups)), dim3(NT), 0, a.stream,
+    hipLaunchKernelGGL((action_vec_kernel<FAM, K, T, IO, C, NT, TRI>), dim3(unsigned(groups)), dim3(NT), 0, a.stream,
                        a.ncells, a.vert, static_cast<const IO *>(a.kappa), static_cast<const IO *>(a.u),
                        static_cast<IO *>(a.y), tab, a.err, al, be);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
@@ -586,6 +636,9 @@ int launch_action_one(const LaunchArgs &a, const T *tab)
 template <int FAM, int K>
 int launch_action_k(const LaunchArgs &a)
 {
+    if (a.trilinear) // per-point geometry: FP64 contractions and storage
+        return (a.precision == SF_FP64 && a.io == SF_F64) ? launch_action_one<FAM, K, double, double, true>(a, a.tab64)
+                                                         : SF_ERR_UNSUPPORTED;
     if (a.precision == SF_FP64)
         return a.io == SF_F64 ? launch_action_one<FAM, K, double, double>(a, a.tab64)
                               : launch_action_one<FAM, K, double, float>(a, a.tab64);

@@ -29,6 +29,8 @@ STUB(launch_action_vec, const LaunchArgs &)
 STUB(launch_matrix_vec, const LaunchArgs &)
 STUB(launch_action_mixed, const LaunchArgs &)
 STUB(launch_dofmap_q, int, int, int, int, int32_t *, hipStream_t)
+STUB(launch_matrix_qgen, const LaunchArgs &)
+STUB(launch_matrix_coll, const LaunchArgs &)
 #undef STUB
 } // namespace sf
 

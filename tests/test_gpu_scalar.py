@@ -182,8 +182,17 @@ def test_geometry_flags(ctx):
     aff = synth.affine_cells(8, 9)
     _, f = run_action(ctx, op, aff, None, u)
     assert f == 0
-    _, f = run_matrix(ctx, op, aff, None)
-    assert f & sf.SF_FLAG_NONBOX
+    # element matrices: exact on sheared cells in the default (affine) geometry; the
+    # box-cell kernel of a context declared SF_GEOM_BOX flags them instead
+    A, f = run_matrix(ctx, op, aff, None)
+    assert f == 0 and rel_l2(A, oracle.element_matrix("Q", 2, "LAPLACE", aff)) <= TOL64
+    cbox = sf.Context(0)
+    try:
+        sf.sf_set_geometry(cbox, "box")
+        _, f = run_matrix(cbox, op, aff, None)
+        assert f & sf.SF_FLAG_NONBOX
+    finally:
+        cbox.close()
 
 
 @pytest.mark.parametrize("grid,p", [((3, 2, 4), 1), ((4, 4, 4), 2), ((2, 3, 5), 5), ((3, 3, 3), 8)])

@@ -151,3 +151,45 @@ def test_full_size_48cubed_sampled(ctx, family, k):
     idx = np.unique(np.concatenate([np.linspace(0, n - 1, 40).astype(np.int64), [n - 1]]))
     ref = oracle.action(family, k, FORM[family], V[idx], u[idx])
     assert rel_l2(y[idx], ref) <= TOL64
+
+
+@pytest.fixture(scope="module")
+def ctx_tri(lib):
+    c = sf.Context(0)
+    sf.sf_set_geometry(c, "trilinear")
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("family", ["NCF", "NCE"])
+@pytest.mark.parametrize("k", range(1, 7))
+@pytest.mark.parametrize("form,alpha,beta", [("MASS", 1.0, 0.0), ("DIVCURL", 0.8, 1.4)])
+def test_action_trilinear_cells(ctx_tri, family, k, form, alpha, beta):
+    """General trilinear cells (SF_GEOM_TRILINEAR): the Piola factors J^T J / |J|,
+    |J| G G^T and 1 / |J| at every quadrature point, against the oracle's direct
+    quadrature with the trilinear map evaluated point by point."""
+    f = FORM[family] if form == "DIVCURL" else "MASS"
+    n = {1: 40, 2: 25, 3: 13, 4: 9, 5: 5, 6: 4}[k]
+    V = synth.trilinear_cells(n, 190 + k)
+    nd = oracle.ndof(family, k)
+    kap = synth.kappa(n, (k + 1) ** 3, 190 + k)
+    u = synth.dof_vector(n, nd, 190 + k)
+    print("case trilinear", family, k, f, n, flush=True)
+    y, flags = gpu_action(ctx_tri, sf.make_op(family, k, f, alpha=alpha, beta=beta), V, kap, u)
+    ref = oracle.action(family, k, f, V, u, kappa=kap, alpha=alpha, beta=beta)
+    assert flags == 0
+    assert rel_l2(y, ref) <= TOL64, (rel_l2(y, ref), max_cell_rel(y, ref))
+
+
+def test_trilinear_cells_flag_and_reject_low_precision(ctx_tri):
+    V = synth.trilinear_cells(4, 199)
+    V[1, 7] = V[1, 0] - 0.9 * (V[1, 7] - V[1, 0])
+    nd = oracle.ndof("NCE", 2)
+    _, flags = gpu_action(ctx_tri, sf.make_op("NCE", 2, "HCURL"), V, None, synth.dof_vector(4, nd, 199))
+    assert flags & sf.SF_FLAG_DETJ
+    for prec, io in (("fp32", "f64"), ("fp64", "f32")):
+        with pytest.raises(sf.SfError) as e:
+            gpu_action(ctx_tri, sf.make_op("NCF", 2, "HDIV", precision=prec, io=io), synth.trilinear_cells(2, 198),
+                       None, synth.dof_vector(2, oracle.ndof("NCF", 2), 198),
+                       io=np.float32 if io == "f32" else np.float64)
+        assert e.value.code == sf.SF_ERR_UNSUPPORTED
