@@ -216,6 +216,28 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
                     const void *kappa, const void *u, void *y, void *hip_stream);
 
 /*
+ * Allocation-free box-cell action, for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors as
+ * assemble_action() on a context whose geometry is SF_GEOM_BOX, restricted
+ * to the box-cell kernel: families SF_Q, SF_DQ, SF_QGLL, forms SF_MASS and
+ * SF_LAPLACE, precision SF_FP64 or SF_FP32, storage SF_F64 or SF_F32
+ * (SF_ERR_UNSUPPORTED otherwise); every cell must be an axis-aligned box (a
+ * sheared cell raises SF_FLAG_NONBOX), whatever the context's geometry hint.
+ * The call allocates nothing: the kernel's scratch (one slot of claim
+ * counters) and the 1-D tables of every supported family and degree live in
+ * a fixed 96 KiB device array per GPU, set up once per device by
+ * sf_context_create and held until the process ends.  The counters are
+ * cleared by a kernel at the start of each call; calls that overlap on one
+ * GPU (different streams, or different host threads) share that array and
+ * race, so they must be serialised by the caller.  Inputs of any size are
+ * accepted (the scratch does not grow with ncells); degrees outside 1..8 are
+ * rejected with SF_ERR_UNSUPPORTED.
+ */
+int assemble_action_box_noalloc(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
+                                const void *kappa, const void *u, void *y, void *hip_stream);
+
+/*
  * Element matrices (Sec. 3.2: argument factorisation, then sum
  * factorisation of every product, Alg. 1, with the products' final
  * contraction merged by distributivity, Sec. 3.6 pass 6):

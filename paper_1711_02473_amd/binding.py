@@ -67,6 +67,7 @@ def load(path=LIB_PATH):
         "sf_set_geometry": ([vp, i32], ctypes.c_int),
         "assemble_action": ([vp, opp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "assemble_element_matrix": ([vp, opp, i64, vp, vp, vp, vp], ctypes.c_int),
+        "assemble_action_box_noalloc": ([vp, opp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "assemble_action_global_q": ([vp, opp, i32, i32, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "sf_check_errors": ([vp, vp, ip], ctypes.c_int),
         "sf_dof_map_q": ([vp, i32, i32, i32, i32, vp, vp], ctypes.c_int),
@@ -159,6 +160,12 @@ def sf_element_dims(op):
 def assemble_action(ctx, op, ncells, vertices, kappa, u, y, stream=None):
     return _check(_lib().assemble_action(ctx.handle, ctypes.byref(op), int(ncells), _ptr(vertices), _ptr(kappa),
                                          _ptr(u), _ptr(y), _stream(stream)), "assemble_action")
+
+
+def assemble_action_box_noalloc(ctx, op, ncells, vertices, kappa, u, y, stream=None):
+    return _check(_lib().assemble_action_box_noalloc(ctx.handle, ctypes.byref(op), int(ncells), _ptr(vertices),
+                                                     _ptr(kappa), _ptr(u), _ptr(y), _stream(stream)),
+                  "assemble_action_box_noalloc")
 
 
 def assemble_action_global_q(ctx, op, nx, ny, nz, vertices, kappa, u_global, y_global, stream=None):

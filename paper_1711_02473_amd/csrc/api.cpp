@@ -328,6 +328,12 @@ int sf_context_create(int hip_device, sf_context **out)
         delete ctx;
         return SF_ERR_HIP;
     }
+    // the allocation-free entry point's scratch array on this device (once per device)
+    if (const int nrc = noalloc_setup(hip_device)) {
+        (void)hipFree(ctx->d_err);
+        delete ctx;
+        return nrc;
+    }
     if (hipMalloc(&ctx->d_sched, sizeof(int) * kSchedSlotInts * kSchedSlots) != hipSuccess) {
         (void)hipFree(ctx->d_err);
         delete ctx;
@@ -418,6 +424,41 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
     }
     a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
     return launch_action_vec(a);
+}
+
+int assemble_action_box_noalloc(sf_context *ctx, const sf_op *op, int64_t ncells, const double *vertices,
+                                const void *kappa, const void *u, void *y, void *hip_stream)
+{
+    if (!ctx || !op || ncells < 0) return SF_ERR_ARG;
+    Dims d;
+    int rc = check_op(op, &d);
+    if (rc) return rc;
+    if (!scalar_family(op->family) || (op->form != SF_MASS && op->form != SF_LAPLACE) ||
+        (op->precision != SF_FP64 && op->precision != SF_FP32))
+        return SF_ERR_UNSUPPORTED;
+    if (ncells == 0) return SF_OK;
+    if (!vertices || !u || !y || y == u || y == kappa) return SF_ERR_ARG;
+    // no make_args: its table cache allocates; the tables come from the scratch array
+    LaunchArgs a{};
+    a.family = op->family;
+    a.degree = op->degree;
+    a.form = op->form;
+    a.nq = d.nq1;
+    a.n0 = d.n0;
+    a.n1 = d.n1;
+    a.precision = op->precision;
+    a.io = op->io_dtype;
+    a.alpha = op->alpha;
+    a.beta = op->beta;
+    a.ncells = ncells;
+    a.vert = vertices;
+    a.kappa = kappa;
+    a.u = u;
+    a.y = y;
+    a.err = ctx->d_err;
+    a.stream = static_cast<hipStream_t>(hip_stream);
+    a.variant = tuned_variant_of(ctx, op, "standalone", 0);
+    return launch_action_box_noalloc(a, ctx->device);
 }
 
 int assemble_action_global_q(sf_context *ctx, const sf_op *op, int32_t nx, int32_t ny, int32_t nz,

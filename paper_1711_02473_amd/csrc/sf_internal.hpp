@@ -110,6 +110,11 @@ int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);
 
 // host-side table block of one element (TabLayout order, FP64)
 int host_table_block(int family, int n0, int n1, int nq1, std::vector<double> &h);
+// allocation-free box-cell action: per-device scratch set up once per device
+// (called by sf_context_create with the device current), then launches that
+// use only the scratch array's device address
+int noalloc_setup(int device);
+int launch_action_box_noalloc(LaunchArgs a, int device);
 
 // tuning keys: what = "batch" (cell groups per tile) or "standalone" (kernel variant)
 std::string tune_key(const sf_op *op, const char *what);

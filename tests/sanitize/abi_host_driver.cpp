@@ -31,6 +31,8 @@ STUB(launch_action_mixed, const LaunchArgs &)
 STUB(launch_dofmap_q, int, int, int, int, int32_t *, hipStream_t)
 STUB(launch_matrix_qgen, const LaunchArgs &)
 STUB(launch_matrix_coll, const LaunchArgs &)
+STUB(noalloc_setup, int)
+STUB(launch_action_box_noalloc, LaunchArgs, int)
 #undef STUB
 } // namespace sf
 
@@ -174,6 +176,15 @@ int main()
         sf_op svk5{SF_Q, 5, SF_SVK, 0, SF_FP64, SF_F64, 1.0, 1.0};
         CHECK(assemble_element_matrix(&ctx, &svk5, 4, dummy, nullptr, dummy, nullptr) == SF_ERR_UNSUPPORTED);
         CHECK(assemble_element_matrix(&ctx, &op, 4, dummy, dummy, dummy, nullptr) == SF_ERR_ARG);
+        sf_op lowp{SF_Q, 3, SF_LAPLACE, 0, SF_BF16, SF_F64, 1.0, 1.0};
+        CHECK(assemble_action_box_noalloc(&ctx, &lowp, 4, dummy, nullptr, dummy, dummy + 1, nullptr) ==
+              SF_ERR_UNSUPPORTED);
+        sf_op ncf{SF_NCF, 2, SF_HDIV, 0, SF_FP64, SF_F64, 1.0, 1.0};
+        CHECK(assemble_action_box_noalloc(&ctx, &ncf, 4, dummy, nullptr, dummy, dummy + 1, nullptr) ==
+              SF_ERR_UNSUPPORTED);
+        CHECK(assemble_action_box_noalloc(&ctx, &op, 4, dummy, nullptr, dummy, dummy, nullptr) == SF_ERR_ARG);
+        CHECK(assemble_action_box_noalloc(nullptr, &op, 4, dummy, nullptr, dummy, dummy + 1, nullptr) == SF_ERR_ARG);
+        CHECK(assemble_action_box_noalloc(&ctx, &op, 0, nullptr, nullptr, nullptr, nullptr, nullptr) == SF_OK);
         sf_op glob{SF_DQ, 2, SF_LAPLACE, 0, SF_FP64, SF_F64, 1.0, 1.0};
         CHECK(assemble_action_global_q(&ctx, &glob, 2, 2, 2, dummy, nullptr, dummy, dummy + 1, nullptr) ==
               SF_ERR_UNSUPPORTED);
