@@ -9,7 +9,8 @@ local-DOF rates, roofline fractions and the mixed-precision comparison are
 reported beside it.  Inputs are resident in HBM before timing; several input
 copies are rotated so that every launch streams more than the 256 MB
 last-level cache.  Kernel durations come from HIP events recorded on the
-stream the kernels run on.  The library is told that every cell is a box
+stream the kernels run on; each degree's time is the median over the timed
+steps (side legs: the median over their repetitions).  The library is told that every cell is a box
 (sf_set_geometry) and each degree's kernel variant is autotuned first.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -40,18 +41,20 @@ def action_bytes_per_cell(p, io_bytes=8):
 
 
 def action_flops_per_cell(p):
-    """Algorithmic flops per cell of the sum-factorised Laplace action as the
-    kernels perform it: 12 one-axis contractions of 2 n^4 (6 interpolation,
-    6 collocated derivative) plus the symmetric pointwise factor (~21 n^3)."""
+    """Algorithmic flops per cell of the sum-factorised Laplace action on a box
+    (the measurement model of the hot-path scope): 16 one-axis contractions of
+    2 n^4 (forward B/D to values and gradients, their transposes back) plus
+    about 5 n^3 for the pointwise stage.  The kernels reach the same sum with
+    fewer operations (collocated derivative, even-odd tables)."""
     n = p + 1
-    return 24 * n ** 4 + 21 * n ** 3
+    return 32 * n ** 4 + 5 * n ** 3
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--degrees", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
@@ -110,13 +113,14 @@ def main():
                 tuned = json.load(f)
         with tempfile.TemporaryDirectory() as td:
             path = os.path.join(td, "tune.json")
-            for p in degrees:
-                key = "gfx950|fam0|p%d|form1|nq%d|prec0|io0|standalone" % (p, p + 1)
-                if args.tune == "run" or key not in tuned:
-                    sf.sf_autotune(ctx, ops[p], ncells, path)
+            for op, keys in tuning_classes(sf, degrees, [int(x) for x in args.mixed_degrees.split(",") if x],
+                                           [x for x in args.legs.split(",") if x]):
+                if args.tune == "run" or any(k not in tuned for k in keys):
+                    sf.sf_autotune(ctx, op, ncells, path)
             if os.path.exists(path):
                 with open(path) as f:
                     tuned.update(json.load(f))
+                sf.sf_load_tuning(ctx, path)
         if args.save_tuning:
             with open(args.save_tuning, "w") as f:
                 json.dump(tuned, f, indent=1, sort_keys=True)
@@ -146,7 +150,8 @@ def main():
             ev[p].append(timers[p])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = {p: float(np.mean([a.elapsed_time(b) for a, b in ev[p]])) for p in degrees}
+    ms = {p: float(np.median([a.elapsed_time(b) for a, b in ev[p]])) for p in degrees}
+    ms_mean = {p: float(np.mean([a.elapsed_time(b) for a, b in ev[p]])) for p in degrees}
 
     glob = {p: (NCELL1 * p + 1) ** 3 for p in degrees}
     loc = {p: ncells * (p + 1) ** 3 for p in degrees}
@@ -157,22 +162,20 @@ def main():
         t = ms[p] / 1e3
         gbs = action_bytes_per_cell(p) * ncells / t / 1e9
         tfl = action_flops_per_cell(p) * ncells / t / 1e12
-        per_p[str(p)] = {"ms": round(ms[p], 4), "gdofs_global": round(glob[p] / t / 1e9, 3),
+        per_p[str(p)] = {"ms": round(ms[p], 4), "ms_mean": round(ms_mean[p], 4),
+                         "gdofs_global": round(glob[p] / t / 1e9, 3),
                          "gdofs_local": round(loc[p] / t / 1e9, 3), "hbm_gbs": round(gbs, 1),
-                         "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "fp64_tflops": round(tfl, 2)}
+                         "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "fp64_tflops": round(tfl, 2),
+                         "fp64_frac": round(tfl / PEAK_FP64_TFLOPS, 4),
+                         "roof_frac": round(max(gbs / PEAK_HBM_GBS, tfl / PEAK_FP64_TFLOPS), 4)}
     dom = max(degrees, key=lambda p: ms[p])
-    achieved = action_bytes_per_cell(dom) * ncells / (ms[dom] / 1e3) / 1e9
     variant = int(tuned.get("gfx950|fam0|p%d|form1|nq%d|prec0|io0|standalone" % (dom, dom + 1), 0))
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": recorded_traffic(dom, variant),
-                "kernel": "%s Q_%d Laplace FP64 (variant %d)"
-                          % ("action_q_kernel" if variant == 3 else "action_q_fast_kernel", dom, variant),
-                "bytes_per_launch": action_bytes_per_cell(dom) * ncells}
+    roofline = roofline_of(dom, ms[dom], ncells, variant)
 
     mixed = None
     if args.mixed_degrees:
         mixed = mixed_leg(sf, ctx, V, bufs, ncells, [int(x) for x in args.mixed_degrees.split(",")], ms, glob,
-                          max(3, args.steps // 2), stream)
+                          args.steps, stream)
 
     legs = [x for x in args.legs.split(",") if x]
     copy_gbs = measured_copy_gbs()
@@ -199,7 +202,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(degrees, bufs, V, glob, ncells, args.cpu_seconds)
+        cpu = cpu_baseline(degrees, bufs, V, glob, ncells, args.cpu_seconds, mixed)
 
     out = {
         "metric": "GDoF/s of Q_p Laplace action p=1..8; mixed-prec vs FP64 at <=1e-6 rel err",
@@ -211,9 +214,15 @@ def main():
                    % ",".join(map(str, degrees)), "ncells": ncells, "degrees": degrees},
         "roofline": roofline, "cpu_baseline": cpu, "per_p": per_p, "mixed_precision": mixed,
         "tuned_variants": {k.split("|", 1)[1]: v for k, v in tuned.items()},
-        "measured_copy_gbs": round(copy_gbs, 1), "frac_vs_measured_copy": round(achieved / copy_gbs, 4),
+        "measured_copy_gbs": round(copy_gbs, 1), "frac_vs_measured_copy": round(roofline["hbm_gbs"] / copy_gbs, 4),
         "legs": side,
     }
+    if mixed:
+        for row in mixed.values():
+            row.pop("_sample_fp64", None)
+            for r in row.values():
+                if isinstance(r, dict):
+                    r.pop("_sample", None)
     if args.calib_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -225,17 +234,75 @@ def main():
     ctx.close()
 
 
+def tune_key(op, what):
+    return "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|%s" % (op.family, op.degree, op.form, op.degree + 1,
+                                                          op.precision, op.io_dtype, what)
+
+
+def tuning_classes(sf, degrees, mixed_degrees, legs):
+    """Every op class the run times whose kernel choice the autotuner makes, with the
+    choice keys it records: the headline (stand-alone box kernel, batched tiles of
+    actions and element matrices), the mass and collocated legs, the FP32 rows of the
+    mixed-precision leg and the batched BF16 / BF16x3 tiles."""
+    out = []
+    for p in degrees:
+        op = sf.make_op("Q", p, "LAPLACE")
+        out.append((op, [tune_key(op, w) for w in ("standalone", "batch", "batch_matrix")]))
+        if "mass" in legs:
+            op = sf.make_op("Q", p, "MASS")
+            out.append((op, [tune_key(op, "standalone")]))
+        if "collocated" in legs:
+            op = sf.make_op("QGLL", p, "LAPLACE")
+            out.append((op, [tune_key(op, "standalone")]))
+    for p in mixed_degrees:
+        for io in ("f64", "f32"):
+            op = sf.make_op("Q", p, "LAPLACE", precision="fp32", io=io)
+            out.append((op, [tune_key(op, "standalone")]))
+    if "batch" in legs:
+        for p in range(2, 9):
+            for prec in ("bf16", "bf16x3"):
+                op = sf.make_op("Q", p, "LAPLACE", precision=prec)
+                out.append((op, [tune_key(op, "batch")]))
+    return out
+
+
+def roofline_of(p, ms, ncells, variant):
+    """Roofline line of the degree-p Laplace launch: the fraction
+    max(bytes / 8 TB/s, flops / 78.6 TFLOP/s) / t of the algorithmic bytes and
+    flops per launch (the larger term names the bound: "hbm", or "alu" for the
+    FP64 vector FMAs), both fractions beside it; t = the median launch time."""
+    t = ms / 1e3
+    nbytes = action_bytes_per_cell(p) * ncells
+    nflops = action_flops_per_cell(p) * ncells
+    gbs, tfl = nbytes / t / 1e9, nflops / t / 1e12
+    hbm_frac, alu_frac = gbs / PEAK_HBM_GBS, tfl / PEAK_FP64_TFLOPS
+    kernel = "%s Q_%d Laplace FP64 (variant %d)" % ("action_q_kernel" if variant == 3 else "action_q_fast_kernel",
+                                                    p, variant)
+    common = {"traffic": recorded_traffic(p, variant), "kernel": kernel, "time_ms": round(ms, 4),
+              "bytes_per_launch": nbytes, "flops_per_launch": nflops,
+              "hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4),
+              "fp64_tflops": round(tfl, 2), "alu_frac": round(alu_frac, 4)}
+    if alu_frac > hbm_frac:
+        line = {"bound": "alu", "achieved": round(tfl, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4)}
+    else:
+        line = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    line.update(common)
+    return line
+
+
 def source_digest():
-    """SHA-256 over the library's kernel and interface sources (sorted by path; build
-    intermediates beside them are not counted): identifies the kernels a recorded
-    profile was taken from."""
-    import glob
+    """SHA-256 over the sources of the headline kernels (the box-cell action, the
+    general action that low degrees select, and the device building blocks they
+    include): identifies the kernels a recorded counter profile was taken from;
+    any change to them makes the record stale."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1711_02473_amd", "csrc")
-    files = sorted(f for ext in ("hip", "inc", "hpp", "cpp") for f in glob.glob(os.path.join(csrc, "*." + ext))) + \
-        [os.path.join(ROOT, "include", "sf.h")]
+    files = [os.path.join(csrc, f) for f in ("action_q_fast.hip", "action_box_body.inc", "action_q.hip",
+                                             "action_q_body.inc", "sf_device.hpp")]
     for f in files:
         h.update(os.path.relpath(f, ROOT).encode())
         with open(f, "rb") as fh:
@@ -247,19 +314,20 @@ def recorded_traffic(p, variant):
     """HBM bytes per launch of the degree-p action kernel from the committed
     rocprofv3 counter record (FETCH_SIZE and WRITE_SIZE, each scaled by what
     the counter reads for a copy of known size), or None when there is no
-    record for this kernel variant and these sources."""
+    record for this degree, kernel variant and these sources."""
     path = os.path.join(ROOT, "profiles", "action_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha256") != source_digest() or rec.get("p") != p or rec.get("variant") != variant:
+    k = rec.get("kernels", {}).get(str(p))
+    if rec.get("source_sha256") != source_digest() or not k or k.get("variant") != variant:
         return None
-    return rec.get("traffic_bytes")
+    return k.get("traffic_bytes")
 
 
 def timed(fn, reps, stream):
-    """Mean milliseconds of fn() over reps launches, bracketed by HIP events on `stream`."""
+    """Median milliseconds of fn() over reps launches, each bracketed by HIP events on `stream`."""
     import torch
 
     ts = []
@@ -270,7 +338,7 @@ def timed(fn, reps, stream):
         b.record(stream)
         ts.append((a, b))
     torch.cuda.synchronize()
-    return float(np.mean([a.elapsed_time(b) for a, b in ts]))
+    return float(np.median([a.elapsed_time(b) for a, b in ts]))
 
 
 def measured_copy_gbs():
@@ -340,9 +408,9 @@ def trilinear_leg(sf, ncells, degrees, bufs, reps, stream):
 def vq_leg(sf, ctx, V, degrees, reps, stream):
     """Vector Q_p element (3 (p+1)^3 DOFs per cell): the vector Laplace action on the 64^3 box
     mesh (kappa per point U[0.5, 2], u N(0, 1), drawn on the GPU; algorithmic bytes per cell
-    8 (6 n^3 + n^3) + 192), and its block-diagonal element matrices on the first 4096 cells
-    (p = 1..4; bytes written 8 (3 n^3)^2 per cell, of which the off-diagonal two thirds are the
-    cleared buffer)."""
+    8 (6 n^3 + n^3) + 192), and its block-diagonal element matrices on the first cells (p = 1..4,
+    at least 4096 cells and 400 MB of output; bytes written 8 (3 n^3)^2 per cell, of which the
+    off-diagonal two thirds are the cleared buffer)."""
     import torch
 
     from paper_1711_02473_amd import synth
@@ -352,17 +420,21 @@ def vq_leg(sf, ctx, V, degrees, reps, stream):
     for p in degrees:
         n3 = (p + 1) ** 3
         op = sf.make_op("VQ", p, "LAPLACE")
-        kap = synth.device_kappa(ncells, n3, 3, p)
-        _, u = synth.device_displacements(ncells, 3 * n3, 3, p)
-        y = torch.empty_like(u)
-        sf.assemble_action(ctx, op, ncells, V, kap, u, y, stream)
-        ms = timed(lambda it: sf.assemble_action(ctx, op, ncells, V, kap, u, y, stream), reps, stream)
+        # input copies rotated so that every launch streams more than the last-level cache
+        nrot = max(1, min(4, math.ceil(768e6 / (ncells * (8 * 7 * n3 + 192)))))
+        sets = [(synth.device_kappa(ncells, n3, 3 + 10 * r, p), synth.device_displacements(ncells, 3 * n3, 3 + 10 * r, p)[1])
+                for r in range(nrot)]
+        y = torch.empty_like(sets[0][1])
+        sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], y, stream)
+        ms = timed(lambda it: sf.assemble_action(ctx, op, ncells, V, sets[it % nrot][0], sets[it % nrot][1], y, stream),
+                   reps, stream)
         gbs = ncells * (8 * 7 * n3 + 192) / (ms / 1e3) / 1e9
         act[str(p)] = {"ms": round(ms, 4), "gdofs_local": round(ncells * 3 * n3 / (ms / 1e3) / 1e9, 3),
                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
-        del kap, u, y
+        del sets, y
         if p <= 4:
-            nm = 4096
+            # at least 4096 cells and 400 MB of matrices, so that the writes leave the last-level cache
+            nm = int(min(ncells, max(4096, math.ceil(400e6 / (8 * (3 * n3) ** 2)))))
             A = torch.empty((nm, 3 * n3, 3 * n3), dtype=torch.float64, device="cuda")
             kap = synth.device_kappa(nm, n3, 3, p)
             sf.assemble_element_matrix(ctx, op, nm, V[:nm], kap, A, stream)
@@ -403,10 +475,13 @@ def svk_leg(sf, ctx, V, degrees, reps, stream, lam=1.3, mu=0.8):
                        "gdofs_global": round(3 * (64 * p + 1) ** 3 / (ms / 1e3) / 1e9, 3),
                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
         del sets, y
-        if p <= 4:
-            # element matrices of the linearised residual (left-hand-side assembly), first 4096
-            # cells; algorithmic work per cell: 9 blocks x 2 (4 n^7 + 18 n^6 + 9 n^5) flops
-            n, nm = p + 1, 4096
+        if True:
+            # element matrices of the linearised residual (left-hand-side assembly) on the first
+            # cells: at least 4096 cells and 400 MB of output, at most 4 GiB of output;
+            # algorithmic work per cell: 9 blocks x 2 (4 n^7 + 18 n^6 + 9 n^5) flops
+            n = p + 1
+            cb = 8 * (3 * n3) ** 2
+            nm = int(min(ncells, (4 << 30) // cb, max(4096, math.ceil(400e6 / cb))))
             u0 = synth.device_displacements(nm, 3 * n3, 1, p)[0]
             A = torch.empty((nm, 3 * n3, 3 * n3), dtype=torch.float64, device="cuda")
             sf.assemble_element_matrix(ctx, op, nm, V[:nm], u0, A, stream)
@@ -432,19 +507,22 @@ def global_leg(sf, ctx, V, bufs, degrees, glob, reps, stream, n1=NCELL1):
     ncells = n1 ** 3
     for p in degrees:
         op = sf.make_op("Q", p, "LAPLACE")
-        kap = bufs[p][0][0]
         ng = glob[p]
+        bts = 16 * ng + (8 * (p + 1) ** 3 + 192) * ncells
+        # (vertices, kappa, u) copies rotated so that every launch streams more than the
+        # last-level cache (the vertex array alone is 50 MB)
+        nrot = max(2, min(6, math.ceil(768e6 / bts)))
         g = torch.Generator(device="cuda")
         g.manual_seed(171102473 * 1000 + 230 + p)
-        ug = torch.randn((2, ng), generator=g, device="cuda", dtype=torch.float64)
+        ug = torch.randn((nrot, ng), generator=g, device="cuda", dtype=torch.float64)
+        sets = [(V if r == 0 else V.clone(), bufs[p][r % len(bufs[p])][0], ug[r]) for r in range(nrot)]
         y = torch.empty((ng,), device="cuda", dtype=torch.float64)
-        sf.assemble_action_global_q(ctx, op, n1, n1, n1, V, kap, ug[0], y, stream)
-        ms = timed(lambda it: sf.assemble_action_global_q(ctx, op, n1, n1, n1, V, kap, ug[it % 2], y, stream),
-                   reps, stream)
-        bts = 16 * ng + (8 * (p + 1) ** 3 + 192) * ncells
+        sf.assemble_action_global_q(ctx, op, n1, n1, n1, V, sets[0][1], ug[0], y, stream)
+        ms = timed(lambda it: sf.assemble_action_global_q(ctx, op, n1, n1, n1, sets[it % nrot][0], sets[it % nrot][1],
+                                                          sets[it % nrot][2], y, stream), reps, stream)
         out[str(p)] = {"ms": round(ms, 4), "gdofs_global": round(ng / (ms / 1e3) / 1e9, 3),
                        "hbm_gbs": round(bts / (ms / 1e3) / 1e9, 1), "hbm_frac": round(bts / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
-        del ug, y
+        del ug, y, sets
     assert sf.sf_check_errors(ctx) == 0
     return out
 
@@ -492,15 +570,33 @@ def matrix_leg(sf, ctx, V, degrees, stream, budget_bytes=4 << 30):
         n3 = (p + 1) ** 3
         nc = matrix_leg_cells(p, V.shape[0], budget_bytes)
         kap = synth.device_kappa(nc, n3, 2, p)
-        A = torch.empty((nc, n3, n3), device="cuda", dtype=torch.float64)
+        # output buffers rotated so that the written matrices leave the last-level cache
+        nrot = max(1, min(3, math.ceil(600e6 / (8 * n3 * n3 * nc))))
+        As = [torch.empty((nc, n3, n3), device="cuda", dtype=torch.float64) for _ in range(nrot)]
         op = sf.make_op("Q", p, "LAPLACE")
-        sf.assemble_element_matrix(ctx, op, nc, V, kap, A, stream)
-        ms = timed(lambda it: sf.assemble_element_matrix(ctx, op, nc, V, kap, A, stream), 5, stream)
+        sf.assemble_element_matrix(ctx, op, nc, V, kap, As[0], stream)
+        ms = timed(lambda it: sf.assemble_element_matrix(ctx, op, nc, V, kap, As[it % nrot], stream), 10, stream)
         bts = (8 * n3 * n3 + 8 * n3 + 192) * nc
         out[str(p)] = {"cells": nc, "ms": round(ms, 4), "cells_per_s": round(nc / (ms / 1e3), 1),
                        "hbm_gbs": round(bts / (ms / 1e3) / 1e9, 1),
                        "hbm_frac": round(bts / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
-        del kap, A
+        # the final contraction on MFMA (BF16 single term, BF16 x3 split), FP32 accumulation,
+        # FP64 output; error against the FP64 matrices of the same cells
+        sf.assemble_element_matrix(ctx, op, nc, V, kap, As[0], stream)
+        Am = torch.empty_like(As[0])
+        errs = {}
+        for prec in ("bf16", "bf16x3"):
+            sf.assemble_element_matrix(ctx, sf.make_op("Q", p, "LAPLACE", precision=prec), nc, V, kap, Am, stream)
+            errs[prec] = float(torch.linalg.vector_norm(Am - As[0]) / torch.linalg.vector_norm(As[0]))
+        del Am
+        for prec in ("bf16", "bf16x3"):
+            opm = sf.make_op("Q", p, "LAPLACE", precision=prec)
+            err = errs[prec]
+            msm = timed(lambda it: sf.assemble_element_matrix(ctx, opm, nc, V, kap, As[it % nrot], stream), 10,
+                        stream)
+            out[str(p)][prec] = {"ms": round(msm, 4), "hbm_frac": round(bts / (msm / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                                 "speedup_vs_fp64": round(ms / msm, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err)}
+        del kap, As
     assert sf.sf_check_errors(ctx) == 0
     return out
 
@@ -516,8 +612,9 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
     4..16) and degree p_m (uniform in 2..8), Laplace action with kappa per Gauss
     point in one persistent launch replayed from a hipGraph, FP64 and with
     BF16 / BF16 x3 contractions (error against the FP64 batch), then the same
-    meshes' element matrices (FP64) together with the FP64 actions in one
-    launch, matrices written into a per-degree arena of 2 GiB cycled per job."""
+    meshes' element matrices together with the actions in one launch (FP64, and
+    BF16 with the matrices' final contraction on MFMA), matrices written into a
+    per-degree arena of 2 GiB cycled per job."""
     import torch
 
     from paper_1711_02473_amd import synth
@@ -550,8 +647,8 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
                                       u[p].data_ptr() + slab_off[m] * n3 * esz,
                                       ybuf[p].data_ptr() + slab_off[m] * n3 * esz))
             if matrices:
-                js.append(sf.make_job(sf.make_op("Q", p, "LAPLACE"), ncell[m], vp, kp, A=arena[p],
-                                      A_arena_cells=max(1, arena_bytes // (esz * n3 * n3))))
+                js.append(sf.make_job(sf.make_op("Q", p, "LAPLACE", precision=precision), ncell[m], vp, kp,
+                                      A=arena[p], A_arena_cells=max(1, arena_bytes // (esz * n3 * n3))))
         return js
 
     loc = sum(ncell[m] * (p + 1) ** 3 for m, (n, p) in enumerate(wl))
@@ -570,13 +667,15 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
             row["rel_l2_vs_fp64_gpu"] = float("%.3e" % (num / den) ** 0.5)
         out["action_" + prec] = row
         b.close()
-    b = sf.Batch(ctx, jobs("fp64", y, matrices=True, actions=True))
-    b.launch(stream)
-    ms = timed(lambda it: b.launch(stream), 3, stream)
-    out["action_and_matrix_fp64"] = {"ms": round(ms, 3), "hbm_gbs": round((act_bytes + mat_bytes) / (ms / 1e3) / 1e9, 1),
-                                     "hbm_frac": round((act_bytes + mat_bytes) / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
-                                     "matrix_bytes": int(mat_bytes), "tiles_workgroups": list(b.info())}
-    b.close()
+    for prec, yy in (("fp64", y), ("bf16", yb)):
+        b = sf.Batch(ctx, jobs(prec, yy, matrices=True, actions=True))
+        b.launch(stream)
+        ms = timed(lambda it: b.launch(stream), 3, stream)
+        out["action_and_matrix_" + prec] = {
+            "ms": round(ms, 3), "hbm_gbs": round((act_bytes + mat_bytes) / (ms / 1e3) / 1e9, 1),
+            "hbm_frac": round((act_bytes + mat_bytes) / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+            "matrix_bytes": int(mat_bytes), "tiles_workgroups": list(b.info())}
+        b.close()
     assert sf.sf_check_errors(ctx) == 0
     del kap, u, y, yb, arena
     return out
@@ -590,7 +689,9 @@ def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
     storage; rows "_f32io" also store kappa, u and y in FP32 (the inputs are
     rounded once, outside the timed region, and the error is measured against
     the FP64 result of the unrounded inputs, so it includes that rounding).
-    "best_le_1e-6" names, per degree, the fastest row within 1e-6."""
+    "best_le_1e-6" names, per degree, the fastest row within 1e-6.  The outputs of
+    every row on MIXED_SAMPLE cells are kept (key "_sample") for the CPU-baseline
+    leg, which adds each row's error against the oracle on those cells."""
     import torch
 
     modes = [("fp32", "f64"), ("bf16", "f64"), ("fp16", "f64"), ("bf16x3", "f64"), ("fp32", "f32"),
@@ -624,12 +725,14 @@ def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
             torch.cuda.synchronize()
             sf.assemble_action(ctx, op, ncells, V, sets[0][0], sets[0][1], ym, stream)
             err = float(torch.linalg.vector_norm(ym.double() - ref) / torch.linalg.vector_norm(ref))
-            t = float(np.mean([a.elapsed_time(b) for a, b in ts]))
+            t = float(np.median([a.elapsed_time(b) for a, b in ts]))
             key = mode if io == "f64" else mode + "_f32io"
             row[key] = {"ms": round(t, 4), "gdofs_global": round(glob[p] / (t / 1e3) / 1e9, 3),
-                        "speedup_vs_fp64": round(ms64[p] / t, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err)}
+                        "speedup_vs_fp64": round(ms64[p] / t, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err),
+                        "_sample": ym[sample_idx(ncells)].double().cpu().numpy()}
             del sets, ym
         ok = {k: v for k, v in row.items() if v["rel_l2_vs_fp64_gpu"] <= 1e-6}
+        row["_sample_fp64"] = ref[sample_idx(ncells)].cpu().numpy()
         if ok:
             best = max(ok, key=lambda k: ok[k]["speedup_vs_fp64"])
             row["best_le_1e-6"] = {"mode": best, "speedup_vs_fp64": ok[best]["speedup_vs_fp64"]}
@@ -637,10 +740,32 @@ def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
     return out
 
 
-def cpu_baseline(degrees, bufs, V, glob, ncells, budget):
+MIXED_SAMPLE = 24
+
+
+def sample_idx(ncells, n=MIXED_SAMPLE):
+    """Evenly spaced cells, first and last included (the mixed-precision sample)."""
+    import torch
+    return torch.from_numpy(np.linspace(0, ncells - 1, n).astype(np.int64)).cuda()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(degrees, bufs, V, glob, ncells, budget, mixed=None):
     """The FP64 oracle (direct quadrature) on a bounded, evenly spaced sample of
-    the same cells; its rate is extrapolated to the whole mesh.  The sampled GPU
-    outputs are compared with it on the way."""
+    the same cells, on all host threads and on one thread; its rate is
+    extrapolated to the whole mesh.  The sampled GPU outputs are compared with
+    it on the way, the FP64 path and every mixed-precision row (whose outputs
+    on MIXED_SAMPLE cells the mixed leg kept)."""
     import oracle
     import torch
 
@@ -665,10 +790,46 @@ def cpu_baseline(degrees, bufs, V, glob, ncells, budget):
         t_total += dt * ncells / n
         errs[str(p)] = float(np.linalg.norm(yh - ref) / np.linalg.norm(ref))
         samples[str(p)] = n
+    cores = oracle.num_threads()
     value = sum(glob[p] for p in degrees) / t_total / 1e9
-    return {"value": round(value, 6), "unit": "GDoF/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "evenly spaced cells per degree %s of %d, extrapolated to the full mesh" % (samples, ncells),
-            "sample_rel_err_vs_gpu": errs}
+    # one thread, on a sixteenth of each degree's sample (at least 8 cells)
+    t1 = 0.0
+    samples1 = {}
+    oracle.set_num_threads(1)
+    try:
+        for p in degrees:
+            kap, u, _ = bufs[p][0]
+            n = max(8, samples[str(p)] // 16)
+            idx = (np.arange(n) * (ncells // n)).astype(np.int64)
+            it = torch.from_numpy(idx).cuda()
+            uh, kh = u[it].cpu().numpy(), kap[it].cpu().numpy()
+            t0 = time.perf_counter()
+            oracle.action("Q", p, "LAPLACE", Vh[idx], uh, kappa=kh)
+            t1 += (time.perf_counter() - t0) * ncells / n
+            samples1[str(p)] = n
+    finally:
+        oracle.set_num_threads(cores)
+    out = {"value": round(value, 6), "unit": "GDoF/s", "cores": cores, "kind": "oracle",
+           "sample": "evenly spaced cells per degree %s of %d, extrapolated to the full mesh" % (samples, ncells),
+           "cpu_model": cpu_model(),
+           "value_1thread": round(sum(glob[p] for p in degrees) / t1 / 1e9, 7),
+           "sample_1thread": "evenly spaced cells per degree %s, extrapolated" % samples1,
+           "sample_rel_err_vs_gpu": errs}
+    if mixed:
+        # each mixed-precision row's error against the oracle on the kept sample cells
+        idx = sample_idx(ncells).cpu().numpy()
+        for p, row in mixed.items():
+            pp = int(p)
+            kap, u, _ = bufs[pp][0]
+            it = torch.from_numpy(idx).cuda()
+            ref = oracle.action("Q", pp, "LAPLACE", Vh[idx], u[it].cpu().numpy(), kappa=kap[it].cpu().numpy())
+            nr = np.linalg.norm(ref)
+            for key, r in row.items():
+                if isinstance(r, dict) and "_sample" in r:
+                    r["rel_l2_vs_oracle_sampled"] = float("%.3e" % (np.linalg.norm(r["_sample"] - ref) / nr))
+            if "_sample_fp64" in row:
+                row["fp64_rel_l2_vs_oracle_sampled"] = float("%.3e" % (np.linalg.norm(row["_sample_fp64"] - ref) / nr))
+    return out
 
 
 if __name__ == "__main__":

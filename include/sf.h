@@ -105,8 +105,8 @@ enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3, SF_SVK = 4, SF_SV
  *                    in `kappa` (the form's coefficient) as a local vector of
  *                    the same layout, NULL for u0 = 0 (linear elasticity).
  * Quadrature: p+1 points per axis (GL for SF_Q, GLL for SF_QGLL).  FP64
- * contractions and SF_F64 storage only.  Element matrices: SF_SVK only, p <=
- * 4 (SF_ERR_UNSUPPORTED otherwise), kappa = u0 as for the action, output
+ * contractions and SF_F64 storage only.  Element matrices: SF_SVK only
+ * (p = 1..8; 38 MB per cell at p = 8), kappa = u0 as for the action, output
  * [ncells][ndof_cell][ndof_cell] with row = test function (c, i) and column
  * = trial function (c', j): the tangent modulus of P at u0 in every block.
  * Geometry: affine cells, or any trilinear cell under SF_GEOM_TRILINEAR (J
@@ -323,7 +323,11 @@ int64_t sf_plan_axis_order(const int32_t *in, const int32_t *out, int32_t *order
  * (A_arena_cells <= 0 means ncells, i.e. no cycling).  sf_batch_create
  * validates every job, builds the cost-ordered tile list, captures the
  * persistent kernel into a hipGraph on an internal stream and instantiates
- * it; it does not run it.  The caller keeps every job buffer alive until
+ * it; it does not run it.  On a context declared SF_GEOM_BOX the FP64
+ * actions run the box-cell body (cells must be axis-aligned boxes, as for
+ * assemble_action there); otherwise the general affine body.  Supported
+ * jobs: SF_Q, SF_LAPLACE, SF_F64 storage; actions in any precision, element
+ * matrices in SF_FP64.  The caller keeps every job buffer alive until
  * sf_batch_destroy.  Errors: SF_ERR_ARG, SF_ERR_UNSUPPORTED, SF_ERR_NOMEM,
  * SF_ERR_HIP.
  */
@@ -345,18 +349,26 @@ int sf_batch_destroy(sf_batch *batch);
 int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
 
 /*
- * Tile autotuner for the Q_p Laplace action: times, on ncells_hint synthetic
- * unit-box cells on an internal stream, (1) the tile size of the batched
- * launch (1, 2, 4, 8 or 16 cell groups per tile; variants 0..4) and (2) for
- * FP64 / FP32 the stand-alone box-cell kernel variants (0: prefetch of the
- * next cell group, >= 3 workgroups per CU; 1: no prefetch, >= 4; 2:
- * prefetch, >= 2; 3: the general three-tensor kernel that SF_GEOM_AFFINE
- * uses; 4 and 5: 128-thread workgroups with and without prefetch), and
- * records the fastest of each in the context (and, when
- * cache_json_path is non-NULL, merges them into that JSON file, keyed by
- * architecture, family, degree, form, nq1, precision, io dtype and
- * "batch" / "standalone").  Later calls with the same key use the winners.
- * sf_tuned_variant() returns the batched tile variant (default 2).
+ * Autotuner of the kernel choices the library makes per class (family,
+ * degree, form, nq1, precision, storage): times, on ncells_hint synthetic
+ * unit-box cells on an internal stream, the candidates of every choice that
+ * applies to `op` and records the fastest in the context:
+ *   "batch" (SF_Q, SF_LAPLACE, SF_F64 storage, any precision): cell groups
+ *     per tile of the batched launch's actions (1, 2, 4, 8 or 16; variants
+ *     0..4);
+ *   "batch_matrix" (the same class with SF_FP64): cell groups per tile of
+ *     the batched launch's element matrices (same variants);
+ *   "standalone" (SF_Q, SF_DQ, SF_QGLL; SF_MASS, SF_LAPLACE; SF_FP64 or
+ *     SF_FP32; either storage): the box-cell action kernel used under
+ *     SF_GEOM_BOX (0: prefetch of the next cell group, >= 3 workgroups per
+ *     CU; 1: no prefetch, >= 4; 2: prefetch, >= 2; 3: the general
+ *     three-tensor kernel that SF_GEOM_AFFINE uses; 4 and 5: 128-thread
+ *     workgroups with and without prefetch).
+ * When cache_json_path is non-NULL the choices are merged into that JSON
+ * file, keyed by architecture, family, degree, form, nq1, precision, io dtype
+ * and the choice name.  Later calls with the same key use the winners.
+ * Returns SF_ERR_UNSUPPORTED for an op with no tunable choice.
+ * sf_tuned_variant() returns the batched action tile variant (default 2).
  */
 int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const char *cache_json_path);
 int sf_tuned_variant(sf_context *ctx, const sf_op *op, int32_t *variant);

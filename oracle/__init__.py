@@ -12,5 +12,5 @@ the GPU library and the GPU library never imports it.
 from .oracle import (  # noqa: F401
     FAMILIES, FORMS, build, load, gl_rule, gll_rule, lagrange, lagrange_deriv,
     ndof, tabulate, jacobian, element_matrix, action, dofmap_q, global_action_q, concat_index,
-    num_threads, svk_energy, svk_residual, svk_jacobian_action, svk_matrix,
+    num_threads, set_num_threads, svk_energy, svk_residual, svk_jacobian_action, svk_matrix,
 )

@@ -275,3 +275,10 @@ def concat_index(extents, block, multi):
 
 def num_threads():
     return int(load().orc_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP thread count of later oracle calls (the GNU OpenMP runtime the
+    oracle is linked against)."""
+    load()
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))

@@ -20,16 +20,11 @@
 //   consecutive addresses).
 #include <algorithm>
 
+#include "action_box_body.inc"
 #include "sf_device.hpp"
 #include "sf_internal.hpp"
 
 namespace sf {
-
-template <int N, int NQ, int FORM, bool COLL, typename T, int C> struct ActionFastSmem {
-    static constexpr int NB = (FORM == SF_LAPLACE) ? 2 : 1;
-    static constexpr int tensor_bytes = NB * C * Lds3<NQ>::CS * int(sizeof(T));
-    static constexpr int bytes = tensor_bytes + 8 * (6 * C + 24 * C) + 16 * C;
-};
 
 // PREF: prefetch the next group's inputs into registers (more registers,
 // latency overlap) or load them when needed; MINB: workgroups per CU the
@@ -44,70 +39,21 @@ __global__ void __launch_bounds__(NT, MINB)
                          const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab,
                          int *__restrict__ err, int *__restrict__ sched, const int gny = 0, const int gnz = 0)
 {
-    static_assert(N == NQ, "the fast kernel assumes n Gauss points per axis");
     static_assert(!(GLB && COLL), "global vectors are for the continuous family");
-    static_assert(C * N * N <= NT, "one pencil per thread and stage");
-    using L = Lds3<NQ>;
-    constexpr int S1 = L::S1, S2 = L::S2, CS = L::CS;
-    constexpr int NB = (FORM == SF_LAPLACE) ? 2 : 1;
+    using SM = BoxSmem<N, NQ, FORM, COLL, T, C>;
+    __shared__ __align__(16) unsigned char smem[SM::bytes];
     constexpr TabLayout TL(N, 0, NQ);
-    constexpr int N2 = N * N, N3 = N2 * N;
-    // even-odd packed tables: B, B^T centrosymmetric, Dh, Dh^T skew-centrosymmetric
-    const T *const Bt = tab + TL.BEO();
-    const T *const BtT = tab + TL.BTEO();
-    const T *const Dh = tab + TL.DhEO();
-    const T *const DhT = tab + TL.DhTEO();
-    const T *const tW = tab + TL.W();
-
-    __shared__ T lds[NB * C * CS];
-    __shared__ double sP[C][6];
-    __shared__ double sV[C][24];
-    // 1-D weights in LDS for the lane-dependent w[q] factors: a vector global load here
-    // would add a vector-memory wait to every stage that uses them
-    __shared__ T sWq[NQ];
-    T *const L0 = lds;
-    T *const L1 = lds + (NB - 1) * C * CS;
+    constexpr int VR = BoxVR<C, NT>::VR;
+    T *const sWq = reinterpret_cast<T *>(smem + SM::off_W);
 
     const int64_t ngroups = (ncells + C - 1) / C;
     const int tid = threadIdx.x;
-    // this thread's x-pencil in the HBM stages (stage 1: u; the x stage: kappa)
-    const bool pen = tid < C * N2;
-    const int pc = pen ? tid / N2 : 0, pr = tid - pc * N2, pa = pr / N, pb = pr - pa * N;
-    // the group's 24 C vertex coordinates, VR per thread (contiguous in HBM)
-    constexpr int VR = (24 * C + NT - 1) / NT;
-
+    const BoxPencil<N, C, NT> pp;
+    const BoxLattice<N> lat(gny, gnz);
     T ureg[N], kreg[NQ];
     double vreg[VR];
-    auto load_v = [&](int64_t g) {
-#pragma unroll
-        for (int r = 0; r < VR; ++r) {
-            const int t = tid + r * NT;
-            vreg[r] = (t < 24 * C && g * C + t / 24 < ncells) ? vert[g * C * 24 + t] : 0.0;
-        }
-    };
-    // global lattice numbering (GLB): local (i0, i1, i2) of cell (ci, cj, ck) is lattice point
-    // (ci p + i0, cj p + i1, ck p + i2), numbered (a (ny p + 1) + b)(nz p + 1) + c
-    constexpr int P = N - 1;
-    const int64_t lz = int64_t(gnz) * P + 1, lyz = (int64_t(gny) * P + 1) * lz;
-    auto gbase = [&](int64_t gc) {
-        const int64_t ci = gc / (int64_t(gny) * gnz), cj = (gc / gnz) % gny, ck = gc % gnz;
-        return (ci * P) * lyz + (cj * P + pa) * lz + ck * P + pb;
-    };
-    auto load_u = [&](int64_t g) {
-        const int64_t gc = g * C + pc;
-        const bool ok = pen && gc < ncells;
-        if constexpr (GLB) {
-            const int64_t b0 = ok ? gbase(gc) : 0;
-#pragma unroll
-            for (int i = 0; i < N; ++i) ureg[i] = ok ? T(to_d(u[b0 + i * lyz])) : T(0);
-        } else {
-#pragma unroll
-            for (int i = 0; i < N; ++i) ureg[i] = ok ? T(to_d(u[gc * N3 + i * N2 + pr])) : T(0);
-        }
-    };
-    auto load_k = [&](int64_t g) {
-        const int64_t gc = g * C + pc;
-        ld_coeff(kappa, pen && gc < ncells, gc * N3 + pr, N2, kreg);
+    auto load = [&](int64_t g) {
+        box_load<N, NQ, FORM, T, IO, C, NT, GLB>(g * C, ncells, vert, kappa, u, pp, lat, vreg, ureg, kreg);
     };
 
     // Group schedule: groups are dealt round-robin (round r gives workgroup b group
@@ -125,12 +71,8 @@ __global__ void __launch_bounds__(NT, MINB)
     const int64_t rounds = DYN ? (ngroups * 3 / 4) / gridDim.x : 0;
     const int parts = gridDim.x < 8 ? int(gridDim.x) : 8, part = int(blockIdx.x) % parts;
     int64_t g = blockIdx.x, gn = int64_t(blockIdx.x) + gridDim.x, it = 0;
-    if (tid < NQ) sWq[tid] = tW[tid]; // read after the loop's first barrier
-    if (PREF && g < ngroups) {
-        load_v(g);
-        load_u(g);
-        if constexpr (FORM == SF_LAPLACE) load_k(g);
-    }
+    if (tid < NQ) sWq[tid] = tab[TL.W() + tid]; // read after the group body's first barrier
+    if (PREF && g < ngroups) load(g);
     while (g < ngroups) {
         int64_t claim = 0; // the group after gn
         if (tid == 0)
@@ -138,202 +80,11 @@ __global__ void __launch_bounds__(NT, MINB)
                         ? blockIdx.x + (it + 2) * gridDim.x
                         : rounds * gridDim.x + part + int64_t(parts) * atomicAdd(sched + kSchedLine * part, 1);
         const bool more = PREF && gn < ngroups;
-        const int64_t cell0 = g * C;
-        if (!PREF) {
-            load_v(g);
-            load_u(g);
-            if constexpr (FORM == SF_LAPLACE) load_k(g);
-        }
-#pragma unroll
-        for (int r = 0; r < VR; ++r) {
-            const int t = tid + r * NT;
-            if (t < 24 * C) sV[t / 24][t % 24] = vreg[r];
-        }
-        // The next group's inputs are requested once this group has issued its last
-        // global load (vmcnt waits are in order: an earlier prefetch would make every
-        // later wait of this group wait for it too).
-        auto prefetch_next = [&] {
-            if (more) {
-                load_v(gn);
-                load_u(gn);
-                if constexpr (FORM == SF_LAPLACE) load_k(gn);
-            }
-        };
-        __syncthreads(); // vertices staged; the previous group's last LDS reads are done
-
-        // ---- geometry (FP64): J, det, |J| G G^T (or |J|), box test
-        if (tid < C) {
-            double P[6] = {0, 0, 0, 0, 0, 0};
-            if (cell0 + tid < ncells) {
-                double J[3][3], det;
-                int f = affine_jacobian(sV[tid], J, det);
-                if (FORM == SF_LAPLACE) {
-                    laplace_factor(J, det, P);
-                    const double off = fabs(J[0][1]) + fabs(J[0][2]) + fabs(J[1][0]) + fabs(J[1][2]) +
-                                       fabs(J[2][0]) + fabs(J[2][1]);
-                    const double dia = fabs(J[0][0]) + fabs(J[1][1]) + fabs(J[2][2]);
-                    if (off > 1e-14 * dia) f |= SF_FLAG_NONBOX; // only the diagonal of G G^T is applied
-                } else {
-                    P[0] = fabs(det);
-                }
-                if (f) atomicOr(err, f);
-            }
-#pragma unroll
-            for (int t = 0; t < 6; ++t) sP[tid][t] = P[t];
-        }
-
-        if constexpr (COLL && FORM == SF_MASS) {
-            // collocated mass: diagonal operator, y = w kappa |J| u, no LDS tensors
-            __syncthreads();
-            if (pen && cell0 + pc < ncells) {
-                cptr<T> W = fresh(tW);
-                const T s23 = T(sP[pc][0]) * sWq[pa] * sWq[pb];
-                const int64_t base = (cell0 + pc) * N3 + pr;
-                T k[N];
-                ld_coeff(kappa, true, base, N2, k);
-#pragma unroll
-                for (int i = 0; i < N; ++i) y[base + i * N2] = IO(s23 * W[i] * k[i] * ureg[i]);
-            }
-            prefetch_next();
-        } else {
-            // ---- stage 1 (x): u -> B_x u; for the Laplace form kappa is staged in L1
-            // (read back along z, then overwritten by the z stage's output)
-            if (pen) {
-                if constexpr (COLL) {
-                    st_pencil<0, N, S1, S2>(L0 + pc * CS, pa, pb, ureg);
-                } else {
-                    T out[NQ];
-                    apply_eo<N, false, false>(Bt, ureg, out);
-                    st_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, out);
-                }
-                if constexpr (FORM == SF_LAPLACE) st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, kreg);
-            }
-            // kappa along this thread's y-stage pencil (one pencil per thread: C = NT / n^2)
-            T ky[NQ];
-            if constexpr (FORM == SF_LAPLACE) ld_coeff(kappa, pen && cell0 + pc < ncells, (cell0 + pc) * N3 + pa * N2 + pb, NQ, ky);
-            __syncthreads();
-            // ---- stage 2 (y): B_y
-            if constexpr (!COLL) {
-                pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
-                    T in[N], out[NQ];
-                    ld_pencil<1, N, S1, S2>(L0 + c * CS, q1, i3, in);
-                    apply_eo<N, false, false>(Bt, in, out);
-                    st_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, i3, out);
-                });
-                __syncthreads();
-            }
-
-            if constexpr (FORM == SF_MASS) {
-                // ---- stage 3 (z): B_z, w kappa |J|, B_z^T
-                pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
-                    const int64_t gc = cell0 + c;
-                    T in[N], ut[NQ], t[N], k[NQ];
-                    ld_coeff(kappa, gc < ncells, gc * N3 + (q1 * NQ + q2) * NQ, 1, k);
-                    ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
-                    apply_eo<N, false, false>(Bt, in, ut);
-                    cptr<T> W = fresh(tW);
-                    const T w12 = T(sP[c][0]) * sWq[q1] * sWq[q2];
-#pragma unroll
-                    for (int q3 = 0; q3 < NQ; ++q3) ut[q3] *= w12 * W[q3] * k[q3];
-                    apply_eo<N, false, false>(BtT, ut, t);
-                    st_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, t);
-                });
-                prefetch_next();
-                __syncthreads();
-            } else {
-                // ---- box path.  stage 3 (z): u~ = B_z(.), store u~; w = Dh_z^T (w kappa P_zz Dh_z u~)
-                pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
-                    T ut[NQ], gz[NQ], k[NQ];
-                    ld_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, k);
-                    if constexpr (COLL) {
-                        ld_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, ut);
-                    } else {
-                        T in[N];
-                        ld_pencil<2, N, S1, S2>(L0 + c * CS, q1, q2, in);
-                        apply_eo<N, false, false>(Bt, in, ut);
-                        st_pencil<2, NQ, S1, S2>(L0 + c * CS, q1, q2, ut);
-                    }
-                    apply_eo<N, true, false>(Dh, ut, gz);
-                    cptr<T> W = fresh(tW);
-                    const T w12 = T(sP[c][5]) * sWq[q1] * sWq[q2];
-#pragma unroll
-                    for (int q3 = 0; q3 < NQ; ++q3) gz[q3] *= w12 * W[q3] * k[q3];
-                    apply_eo<N, true, false>(DhT, gz, ut);
-                    st_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, ut);
-                });
-                __syncthreads();
-                // ---- stage 4 (y): w += Dh_y^T (w kappa P_yy Dh_y u~)
-                pencils<C, NQ, NQ, NT>([&](int c, int q1, int q3) {
-                    const T(&k)[NQ] = ky; // this thread's only pencil
-                    T ut[NQ], gy[NQ], wv[NQ];
-                    ld_pencil<1, NQ, S1, S2>(L0 + c * CS, q1, q3, ut);
-                    apply_eo<N, true, false>(Dh, ut, gy);
-                    cptr<T> W = fresh(tW);
-                    const T w13 = T(sP[c][3]) * sWq[q1] * sWq[q3];
-#pragma unroll
-                    for (int q2 = 0; q2 < NQ; ++q2) gy[q2] *= w13 * W[q2] * k[q2];
-                    ld_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
-                    apply_eo<N, true, true>(DhT, gy, wv);
-                    st_pencil<1, NQ, S1, S2>(L1 + c * CS, q1, q3, wv);
-                });
-                __syncthreads();
-                // ---- stage 5 (x): w += Dh_x^T (w kappa P_xx Dh_x u~); kappa from registers
-                if (pen) {
-                    T ut[NQ], gx[NQ], wv[NQ];
-                    ld_pencil<0, NQ, S1, S2>(L0 + pc * CS, pa, pb, ut);
-                    apply_eo<N, true, false>(Dh, ut, gx);
-                    cptr<T> W = fresh(tW);
-                    const T w23 = T(sP[pc][0]) * sWq[pa] * sWq[pb];
-#pragma unroll
-                    for (int q1 = 0; q1 < NQ; ++q1) gx[q1] *= w23 * W[q1] * kreg[q1];
-                    ld_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
-                    apply_eo<N, true, true>(DhT, gx, wv);
-                    st_pencil<0, NQ, S1, S2>(L1 + pc * CS, pa, pb, wv);
-                }
-                prefetch_next();
-                __syncthreads();
-                // ---- backward interpolation, z then y then x; the complete w is in L1
-                if constexpr (!COLL) {
-                    pencils<C, NQ, NQ, NT>([&](int c, int q1, int q2) {
-                        T in[NQ], t[N];
-                        ld_pencil<2, NQ, S1, S2>(L1 + c * CS, q1, q2, in);
-                        apply_eo<N, false, false>(BtT, in, t);
-                        st_pencil<2, N, S1, S2>(L1 + c * CS, q1, q2, t);
-                    });
-                    __syncthreads();
-                }
-            }
-            T *const LB = (FORM == SF_LAPLACE) ? L1 : L0; // tensor holding the backward data
-            if constexpr (!COLL) {
-                pencils<C, NQ, N, NT>([&](int c, int q1, int i3) {
-                    T in[NQ], out[N];
-                    ld_pencil<1, NQ, S1, S2>(LB + c * CS, q1, i3, in);
-                    apply_eo<N, false, false>(BtT, in, out);
-                    st_pencil<1, N, S1, S2>(LB + c * CS, q1, i3, out);
-                });
-                __syncthreads();
-            }
-            // ---- last stage (x): B_x^T, store y (coalesced)
-            if (pen && cell0 + pc < ncells) {
-                T in[NQ], out[N];
-                ld_pencil<0, NQ, S1, S2>(LB + pc * CS, pa, pb, in);
-                if constexpr (COLL) {
-#pragma unroll
-                    for (int i = 0; i < N; ++i) out[i] = in[i];
-                } else {
-                    apply_eo<N, false, false>(BtT, in, out);
-                }
-                if constexpr (GLB) {
-                    const int64_t b0 = gbase(cell0 + pc);
-#pragma unroll
-                    for (int i = 0; i < N; ++i) unsafeAtomicAdd(y + b0 + i * lyz, IO(out[i]));
-                } else {
-                    IO *yo = y + (cell0 + pc) * N3 + pr;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) yo[i * N2] = IO(out[i]);
-                }
-            }
-        }
+        if (!PREF) load(g);
+        box_group<N, NQ, FORM, COLL, T, IO, C, NT, GLB>(g * C, ncells, kappa, y, tab, err, smem, pp, lat, vreg, ureg,
+                                                       kreg, [&] {
+                                                           if (more) load(gn);
+                                                       });
         if (tid == 0) s_claim = claim;
         __syncthreads();
         g = gn;

@@ -492,8 +492,11 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
     Dims d;
     int rc = check_op(op, &d);
     if (rc) return rc;
-    if (op->precision != SF_FP64 || op->form == SF_SVK_RESIDUAL) return SF_ERR_UNSUPPORTED;
-    if (op->form == SF_SVK && op->degree > 4) return SF_ERR_UNSUPPORTED;
+    if (op->form == SF_SVK_RESIDUAL) return SF_ERR_UNSUPPORTED;
+    // lower-precision contractions: the box-cell kernel of Q_p / dQ_p (final contraction on MFMA)
+    if (op->precision != SF_FP64 &&
+        (op->precision == SF_FP32 || (op->family != SF_Q && op->family != SF_DQ) || ctx->geometry != SF_GEOM_BOX))
+        return SF_ERR_UNSUPPORTED;
     if (ncells == 0) return SF_OK;
     if (!vertices || !A || A == kappa) return SF_ERR_ARG;
     LaunchArgs a;
@@ -506,7 +509,7 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
     }
     a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
     // collocated families (points = nodes, B = I): the O(n^5) structured assembly, any geometry
-    if (op->family == SF_QGLL || op->family == SF_DQ) return launch_matrix_coll(a);
+    if ((op->family == SF_QGLL || op->family == SF_DQ) && op->precision == SF_FP64) return launch_matrix_coll(a);
     if (scalar_family(op->family) || op->family == SF_VQ)
         return ctx->geometry == SF_GEOM_BOX ? launch_matrix_q(a) : launch_matrix_qgen(a);
     return launch_matrix_vec(a);

@@ -34,13 +34,20 @@ int ensure_tables(sf_context *ctx, const sf_op *op, LaunchArgs &a);
 } // namespace sf
 
 // the per-cell-group device bodies shared with the stand-alone kernels
+#include "action_box_body.inc"
 #include "action_q_body.inc"
 #include "matrix_q_body.inc"
 #include "mixed_body.inc"
 
 namespace sf {
 
-enum { K_ACT_F64 = 0, K_ACT_BF16 = 1, K_ACT_FP16 = 2, K_ACT_BF16X3 = 3, K_MAT_F64 = 4, K_NKIND = 5 };
+// K_ACT_BOX: the FP64 action with the box-cell body (contexts declared SF_GEOM_BOX)
+// K_MAT_BF16 / K_MAT_FP16 / K_MAT_BF16X3: element matrices with the final contraction on MFMA
+enum {
+    K_ACT_F64 = 0, K_ACT_BF16 = 1, K_ACT_FP16 = 2, K_ACT_BF16X3 = 3, K_MAT_F64 = 4, K_ACT_BOX = 5,
+    K_MAT_BF16 = 6, K_MAT_FP16 = 7, K_MAT_BF16X3 = 8, K_NKIND = 9
+};
+constexpr bool is_mat(int kind) { return kind == K_MAT_F64 || kind >= K_MAT_BF16; }
 constexpr int kNT = 256;
 constexpr int kGroupVariants[5] = {1, 2, 4, 8, 16};
 
@@ -70,13 +77,14 @@ template <int N> struct Cls {
     static constexpr int CMAT = (256 / (N * N * N)) > 0 ? 256 / (N * N * N) : 1;
     static constexpr int cells_per_group(int kind)
     {
-        return kind == K_ACT_F64 ? CA : (kind == K_MAT_F64 ? CMAT : CMIX);
+        return (kind == K_ACT_F64 || kind == K_ACT_BOX) ? CA : (is_mat(kind) ? CMAT : CMIX);
     }
     static constexpr int smem(int kind)
     {
-        return kind == K_ACT_F64 ? ActionQSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
-                                 : (kind == K_MAT_F64 ? MatrixQSmem<N, N, SF_LAPLACE, CMAT>::bytes
-                                                      : ActionMixedSmem<N, N, SF_LAPLACE, CMIX>::bytes);
+        return kind == K_ACT_BOX   ? BoxSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
+               : kind == K_ACT_F64 ? ActionQSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
+                                   : (is_mat(kind) ? MatrixQSmem<N, N, SF_LAPLACE, CMAT>::bytes
+                                                        : ActionMixedSmem<N, N, SF_LAPLACE, CMIX>::bytes);
     }
 };
 
@@ -95,12 +103,33 @@ __device__ __noinline__ void run_tile(const BatchJob *__restrict__ jobs, int job
     const int64_t end = first + count < j.ncells ? first + count : j.ncells;
     constexpr int CPG = Cls<N>::cells_per_group(KIND);
     for (int64_t g = first; g < end; g += CPG) {
-        if constexpr (KIND == K_ACT_F64)
+        if constexpr (KIND == K_ACT_BOX) {
+            using SM = BoxSmem<N, N, SF_LAPLACE, false, double, CPG>;
+            constexpr TabLayout TL(N, 0, N);
+            unsigned char *sm = reinterpret_cast<unsigned char *>(batch_smem);
+            const BoxPencil<N, CPG, kNT> pp;
+            const BoxLattice<N> lat(0, 0);
+            double vreg[BoxVR<CPG, kNT>::VR], ureg[N], kreg[N];
+            if (threadIdx.x < N) reinterpret_cast<double *>(sm + SM::off_W)[threadIdx.x] = j.tab64[TL.W() + threadIdx.x];
+            box_load<N, N, SF_LAPLACE, double, double, CPG, kNT, false>(g, end, j.vert, j.kappa, j.u, pp, lat, vreg,
+                                                                       ureg, kreg);
+            box_group<N, N, SF_LAPLACE, false, double, double, CPG, kNT, false>(g, end, j.kappa, j.y, j.tab64, err, sm, pp,
+                                                                             lat, vreg, ureg, kreg, [] {});
+        } else if constexpr (KIND == K_ACT_F64)
             action_q_body<N, N, SF_LAPLACE, false, double, double, CPG, kNT>(g, end, j.vert, j.kappa, j.u, j.y, j.tab64,
                                                                             err, batch_smem);
         else if constexpr (KIND == K_MAT_F64)
             matrix_q_body<N, N, SF_LAPLACE, double, CPG, kNT>(g, end, j.vert, j.kappa, j.A, j.arena, j.tab64, err,
                                                              batch_smem);
+        else if constexpr (KIND == K_MAT_BF16)
+            matrix_q_body<N, N, SF_LAPLACE, double, CPG, kNT, 1, SF_BF16>(g, end, j.vert, j.kappa, j.A, j.arena,
+                                                                         j.tab64, err, batch_smem);
+        else if constexpr (KIND == K_MAT_FP16)
+            matrix_q_body<N, N, SF_LAPLACE, double, CPG, kNT, 1, SF_FP16>(g, end, j.vert, j.kappa, j.A, j.arena,
+                                                                         j.tab64, err, batch_smem);
+        else if constexpr (KIND == K_MAT_BF16X3)
+            matrix_q_body<N, N, SF_LAPLACE, double, CPG, kNT, 1, SF_BF16X3>(g, end, j.vert, j.kappa, j.A, j.arena,
+                                                                           j.tab64, err, batch_smem);
         else if constexpr (KIND == K_ACT_BF16)
             action_mixed_body<N, N, SF_LAPLACE, false, SF_BF16, double, CPG, kNT>(g, end, j.vert, j.kappa, j.u, j.y,
                                                                                  j.tab64, j.mix, err, batch_smem);
@@ -124,6 +153,10 @@ __device__ __forceinline__ void run_kind(int kind, const BatchJob *jobs, int job
     case K_ACT_FP16: run_tile<N, K_ACT_FP16>(jobs, job, first, count, err); break;
     case K_ACT_BF16X3: run_tile<N, K_ACT_BF16X3>(jobs, job, first, count, err); break;
     case K_MAT_F64: run_tile<N, K_MAT_F64>(jobs, job, first, count, err); break;
+    case K_ACT_BOX: run_tile<N, K_ACT_BOX>(jobs, job, first, count, err); break;
+    case K_MAT_BF16: run_tile<N, K_MAT_BF16>(jobs, job, first, count, err); break;
+    case K_MAT_FP16: run_tile<N, K_MAT_FP16>(jobs, job, first, count, err); break;
+    case K_MAT_BF16X3: run_tile<N, K_MAT_BF16X3>(jobs, job, first, count, err); break;
     default: break;
     }
 }
@@ -196,15 +229,23 @@ int cls_smem(int kind, int n)
 double cls_cost(int kind, int n)
 {
     const double n3 = double(n) * n * n;
-    if (kind == K_MAT_F64) return 8.0 * n3 * n3 + 4.0 * n3 * n3 * n / 10.0;
+    if (is_mat(kind)) return 8.0 * n3 * n3 + 4.0 * n3 * n3 * n / 10.0;
     return 24.0 * n3 + 192.0 + 24.0 * n3 * n / 10.0;
 }
 
-int kind_of(const sf_job &j)
+int kind_of(const sf_job &j, bool box)
 {
-    if (j.A) return K_MAT_F64;
+    if (j.A) {
+        switch (j.op.precision) {
+        case SF_FP64: return K_MAT_F64;
+        case SF_BF16: return K_MAT_BF16;
+        case SF_FP16: return K_MAT_FP16;
+        case SF_BF16X3: return K_MAT_BF16X3;
+        default: return -1;
+        }
+    }
     switch (j.op.precision) {
-    case SF_FP64: return K_ACT_F64;
+    case SF_FP64: return box ? K_ACT_BOX : K_ACT_F64;
     case SF_BF16: return K_ACT_BF16;
     case SF_FP16: return K_ACT_FP16;
     case SF_BF16X3: return K_ACT_BF16X3;
@@ -212,9 +253,9 @@ int kind_of(const sf_job &j)
     }
 }
 
-int groups_for(sf_context *ctx, const sf_op *op)
+int groups_for(sf_context *ctx, const sf_op *op, bool matrix)
 {
-    const int v = tuned_variant_of(ctx, op, "batch", 2);
+    const int v = matrix ? tuned_variant_of(ctx, op, "batch_matrix", 0) : tuned_variant_of(ctx, op, "batch", 2);
     return kGroupVariants[std::min(std::max(v, 0), 4)];
 }
 
@@ -263,10 +304,10 @@ static int batch_build(sf_context *ctx, const sf_job *jobs, int32_t njobs, const
         if (j.ncells < 0) return SF_ERR_ARG;
         if (j.op.family != SF_Q || j.op.form != SF_LAPLACE || j.op.io_dtype != SF_F64) return SF_ERR_UNSUPPORTED;
         const bool mat = j.A != nullptr;
-        if (mat && (j.u || j.y || j.op.precision != SF_FP64)) return SF_ERR_ARG;
+        if (mat && (j.u || j.y)) return SF_ERR_ARG;
         if (!mat && (!j.u || !j.y || j.y == j.u)) return SF_ERR_ARG;
         if (j.ncells > 0 && !j.vertices) return SF_ERR_ARG;
-        const int kind = kind_of(j);
+        const int kind = kind_of(j, ctx->geometry == SF_GEOM_BOX);
         if (kind < 0) return SF_ERR_UNSUPPORTED;
         LaunchArgs a;
         rc = ensure_tables(ctx, &j.op, a);
@@ -287,7 +328,7 @@ static int batch_build(sf_context *ctx, const sf_job *jobs, int32_t njobs, const
         if (j.ncells == 0) continue;
         smem = std::max(smem, cls_smem(kind, n));
         const int cpg = cls_cells_per_group(kind, n);
-        const int g = mat ? 1 : (groups_override ? groups_override[i] : groups_for(ctx, &j.op));
+        const int g = groups_override ? groups_override[i] : groups_for(ctx, &j.op, mat);
         const int64_t per = int64_t(cpg) * g;
         for (int64_t f = 0; f < j.ncells; f += per) {
             BatchTile t;
@@ -309,6 +350,12 @@ static int batch_build(sf_context *ctx, const sf_job *jobs, int32_t njobs, const
 
     sf_batch *b = new (std::nothrow) sf_batch();
     if (!b) return SF_ERR_NOMEM;
+    // a failing HIP call is reported on stderr with its step before the error code
+    auto hip_fail = [&](const char *what) {
+        std::fprintf(stderr, "sf_batch_create: %s failed (%s)\n", what, hipGetErrorString(hipGetLastError()));
+        batch_free(b);
+        return SF_ERR_HIP;
+    };
     b->ctx = ctx;
     b->ntiles = int64_t(sorted.size());
     b->smem = smem;
@@ -320,30 +367,21 @@ static int batch_build(sf_context *ctx, const sf_job *jobs, int32_t njobs, const
     }
     if ((!hj.empty() && hipMemcpy(b->d_jobs, hj.data(), sizeof(BatchJob) * hj.size(), hipMemcpyHostToDevice) != hipSuccess) ||
         (!sorted.empty() &&
-         hipMemcpy(b->d_tiles, sorted.data(), sizeof(BatchTile) * sorted.size(), hipMemcpyHostToDevice) != hipSuccess)) {
-        batch_free(b);
-        return SF_ERR_HIP;
-    }
+         hipMemcpy(b->d_tiles, sorted.data(), sizeof(BatchTile) * sorted.size(), hipMemcpyHostToDevice) != hipSuccess))
+        return hip_fail("copying the job and tile lists");
     int per_cu = 0, ncu = 0;
     if (smem > 64 * 1024 &&
         hipFuncSetAttribute((const void *)batch_persistent_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, smem) !=
-            hipSuccess) {
-        batch_free(b);
-        return SF_ERR_HIP;
-    }
+            hipSuccess)
+        return hip_fail("raising the kernel's LDS limit");
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_persistent_kernel, kNT, size_t(smem)) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
-        batch_free(b);
-        return SF_ERR_HIP;
-    }
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+        return hip_fail("the occupancy query");
     per_cu = std::max(per_cu, 1);
     b->nwg = int(std::min<int64_t>(std::max<int64_t>(b->ntiles, 1), int64_t(per_cu) * ncu));
 
     hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-        batch_free(b);
-        return SF_ERR_HIP;
-    }
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return hip_fail("creating the capture stream");
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, b->d_counter);
@@ -353,10 +391,7 @@ static int batch_build(sf_context *ctx, const sf_job *jobs, int32_t njobs, const
     }
     ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
     (void)hipStreamDestroy(s);
-    if (!ok) {
-        batch_free(b);
-        return SF_ERR_HIP;
-    }
+    if (!ok) return hip_fail("capturing and instantiating the graph");
     *out = b;
     return SF_OK;
 }
@@ -398,12 +433,13 @@ bool write_json(const char *path, const std::map<std::string, int> &m)
     return bool(f);
 }
 
-__global__ void tune_fill_kernel(int64_t ncells, int n3, int nq3, double *vert, double *u, double *kap)
+template <typename IO>
+__global__ void tune_fill_kernel(int64_t ncells, int n3, int nq3, double *vert, IO *u, IO *kap)
 {
     const int64_t total = ncells * std::max(std::max(n3, nq3), 24);
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
-        if (t < ncells * n3) u[t] = double((t * 2654435761LL) % 1000) * 1e-3 - 0.5;
-        if (t < ncells * nq3) kap[t] = 1.0 + double((t * 40503LL) % 1000) * 1e-3;
+        if (t < ncells * n3) u[t] = IO(double((t * 2654435761LL) % 1000) * 1e-3 - 0.5);
+        if (t < ncells * nq3) kap[t] = IO(1.0 + double((t * 40503LL) % 1000) * 1e-3);
         if (t < ncells * 24) {
             const int v = int((t % 24) / 3), a = int(t % 3);
             vert[t] = double((v >> (2 - a)) & 1);
@@ -466,59 +502,101 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
     int nd, nq;
     int rc = op_dims(op, &nd, &nq);
     if (rc) return rc;
-    if (op->family != SF_Q || op->form != SF_LAPLACE || op->io_dtype != SF_F64) return SF_ERR_UNSUPPORTED;
+    const bool scalar = op->family == SF_Q || op->family == SF_DQ || op->family == SF_QGLL;
+    // classes with a choice: the batched launch's tiles (Q_p Laplace, FP64 storage: actions in
+    // every precision, element matrices in FP64) and the stand-alone box-cell action kernel
+    // (scalar families, mass and Laplace, FP64 / FP32 contractions, either storage)
+    const bool tune_batch = op->family == SF_Q && op->form == SF_LAPLACE && op->io_dtype == SF_F64 &&
+                            op->precision != SF_FP32; // the batched launch has no FP32 kind
+    const bool tune_matrix = tune_batch && op->precision == SF_FP64;
+    const bool tune_sa = scalar && (op->form == SF_MASS || op->form == SF_LAPLACE) &&
+                         (op->precision == SF_FP64 || op->precision == SF_FP32);
+    if (!tune_batch && !tune_sa) return SF_ERR_UNSUPPORTED;
     const int64_t nc = std::min<int64_t>(ncells_hint, 1 << 20);
+    const size_t esz = op->io_dtype == SF_F32 ? 4 : 8;
+    // element matrices of at most 512 MiB for the matrix tiles
+    const int64_t mat_cells = std::max<int64_t>(1, std::min<int64_t>(nc, (int64_t(512) << 20) / (8 * int64_t(nd) * nd)));
     // synthetic unit boxes, u and a kappa per quadrature point, as in a production call
-    double *vert = nullptr, *u = nullptr, *y = nullptr, *kap = nullptr;
-    if (hipMalloc(&vert, sizeof(double) * 24 * nc) != hipSuccess || hipMalloc(&u, sizeof(double) * nd * nc) != hipSuccess ||
-        hipMalloc(&y, sizeof(double) * nd * nc) != hipSuccess || hipMalloc(&kap, sizeof(double) * nq * nc) != hipSuccess) {
+    double *vert = nullptr, *A = nullptr;
+    void *u = nullptr, *y = nullptr, *kap = nullptr;
+    if (hipMalloc(&vert, sizeof(double) * 24 * nc) != hipSuccess || hipMalloc(&u, esz * nd * nc) != hipSuccess ||
+        hipMalloc(&y, esz * nd * nc) != hipSuccess || hipMalloc(&kap, esz * nq * nc) != hipSuccess ||
+        (tune_matrix && hipMalloc(&A, sizeof(double) * nd * nd * mat_cells) != hipSuccess)) {
         (void)hipFree(vert);
         (void)hipFree(u);
         (void)hipFree(y);
+        (void)hipFree(kap);
+        (void)hipFree(A);
         return SF_ERR_NOMEM;
     }
-    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, 0, nc, nd, nq, vert, u, kap);
+    if (esz == 4)
+        hipLaunchKernelGGL(tune_fill_kernel<float>, dim3(1024), dim3(256), 0, 0, nc, nd, nq, vert,
+                           static_cast<float *>(u), static_cast<float *>(kap));
+    else
+        hipLaunchKernelGGL(tune_fill_kernel<double>, dim3(1024), dim3(256), 0, 0, nc, nd, nq, vert,
+                           static_cast<double *>(u), static_cast<double *>(kap));
     hipStream_t s;
     hipEvent_t e0, e1;
     bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
-    int best = 2;
-    float best_ms = 1e30f;
-    for (int v = 0; ok && v < 5; ++v) {
-        sf_job j;
-        std::memset(&j, 0, sizeof j);
-        j.op = *op;
-        j.ncells = nc;
-        j.vertices = vert;
-        j.kappa = kap;
-        j.u = u;
-        j.y = y;
-        int g = kGroupVariants[v];
-        sf_batch *b = nullptr;
-        if (batch_build(ctx, &j, 1, &g, &b) != SF_OK) {
-            ok = false;
-            break;
-        }
-        ok = hipGraphLaunch(b->exec, s) == hipSuccess; // warm-up
-        float tot = 0.0f;
+    // median-free, noise-robust timing: the sum of three launches after one warm-up;
+    // a later variant must be 2% faster than the best so far (stable choices)
+    auto time3 = [&](auto &&run) {
+        float tot = -1.0f;
+        if (!ok || !(ok = run())) return tot;
+        tot = 0.0f;
         for (int r = 0; ok && r < 3; ++r) {
-            ok = hipEventRecord(e0, s) == hipSuccess && hipGraphLaunch(b->exec, s) == hipSuccess &&
-                 hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            ok = hipEventRecord(e0, s) == hipSuccess && run() && hipEventRecord(e1, s) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.0f;
             ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
             tot += ms;
         }
-        (void)hipStreamSynchronize(s);
-        batch_free(b);
-        if (ok && tot < 0.98f * best_ms) { // a later variant must be 2% faster: stable choices
-            best_ms = tot;
-            best = v;
+        return ok ? tot : -1.0f;
+    };
+    auto tune_tiles = [&](bool matrix, int &best) {
+        float best_ms = 1e30f;
+        for (int v = 0; ok && v < 5; ++v) {
+            sf_job j;
+            std::memset(&j, 0, sizeof j);
+            j.op = *op;
+            j.ncells = matrix ? mat_cells : nc;
+            j.vertices = vert;
+            j.kappa = kap;
+            if (matrix) {
+                j.A = A;
+                j.A_arena_cells = mat_cells;
+            } else {
+                j.u = u;
+                j.y = y;
+            }
+            int g = kGroupVariants[v];
+            sf_batch *b = nullptr;
+            const int brc = batch_build(ctx, &j, 1, &g, &b);
+            if (brc != SF_OK) {
+                std::fprintf(stderr, "sf_autotune: building the %s tile variant %d failed (%s)\n",
+                             matrix ? "matrix" : "action", v, sf_status_string(brc));
+                ok = false;
+                break;
+            }
+            const float t = time3([&] { return hipGraphLaunch(b->exec, s) == hipSuccess; });
+            if (!ok)
+                std::fprintf(stderr, "sf_autotune: timing the %s tile variant %d failed (%s)\n",
+                             matrix ? "matrix" : "action", v, hipGetErrorString(hipGetLastError()));
+            (void)hipStreamSynchronize(s);
+            batch_free(b);
+            if (ok && t < 0.98f * best_ms) {
+                best_ms = t;
+                best = v;
+            }
         }
-    }
-    // stand-alone box-cell action kernel variants (prefetch / occupancy)
-    int best_sa = 0;
-    if (ok && (op->precision == SF_FP64 || op->precision == SF_FP32)) {
+    };
+    int best = 2, best_mat = 0, best_sa = 0;
+    if (tune_batch) tune_tiles(false, best);
+    if (tune_matrix) tune_tiles(true, best_mat);
+    if (ok && tune_sa) {
+        // stand-alone box-cell action kernel variants (prefetch / occupancy; 3 = the general kernel)
         LaunchArgs a;
         ok = ensure_tables(ctx, op, a) == SF_OK;
         float best_sa_ms = 1e30f;
@@ -530,19 +608,15 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
             a.y = y;
             a.stream = s;
             a.variant = v;
-            a.sched = ctx->d_sched + kSchedSlotInts * (ctx->sched_next++ % kSchedSlots);
-            auto run = [&] { return v == 3 ? launch_action_q(a) : launch_action_q_fast(a); };
-            ok = run() == SF_OK; // warm-up
-            float tot = 0.0f;
-            for (int r = 0; ok && r < 3; ++r) {
-                ok = hipEventRecord(e0, s) == hipSuccess && run() == SF_OK &&
-                     hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-                float ms = 0.0f;
-                ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-                tot += ms;
-            }
-            if (ok && tot < 0.98f * best_sa_ms) {
-                best_sa_ms = tot;
+            const float t = time3([&] {
+                a.sched = ctx->d_sched + kSchedSlotInts * (ctx->sched_next++ % kSchedSlots);
+                return (v == 3 ? launch_action_q(a) : launch_action_q_fast(a)) == SF_OK;
+            });
+            if (!ok)
+                std::fprintf(stderr, "sf_autotune: timing the stand-alone variant %d failed (%s)\n", v,
+                             hipGetErrorString(hipGetLastError()));
+            if (ok && t < 0.98f * best_sa_ms) {
+                best_sa_ms = t;
                 best_sa = v;
             }
         }
@@ -555,13 +629,16 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
     (void)hipFree(u);
     (void)hipFree(y);
     (void)hipFree(kap);
+    (void)hipFree(A);
     if (!ok) return SF_ERR_HIP;
-    ctx->tuned[tune_key(op, "batch")] = best;
-    ctx->tuned[tune_key(op, "standalone")] = best_sa;
+    std::map<std::string, int> got;
+    if (tune_batch) got[tune_key(op, "batch")] = best;
+    if (tune_matrix) got[tune_key(op, "batch_matrix")] = best_mat;
+    if (tune_sa) got[tune_key(op, "standalone")] = best_sa;
+    for (auto &kv : got) ctx->tuned[kv.first] = kv.second;
     if (cache_json_path) {
         auto m = read_json(cache_json_path);
-        m[tune_key(op, "batch")] = best;
-        m[tune_key(op, "standalone")] = best_sa;
+        for (auto &kv : got) m[kv.first] = kv.second;
         if (!write_json(cache_json_path, m)) return SF_ERR_ARG;
     }
     return SF_OK;

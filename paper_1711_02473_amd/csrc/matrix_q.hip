@@ -23,6 +23,7 @@
 // block is written as one contiguous n^3-long run (coalesced).
 #include "sf_device.hpp"
 #include "sf_internal.hpp"
+#include "mixed_body.inc"
 #include "matrix_q_body.inc"
 
 namespace sf {
@@ -30,13 +31,16 @@ namespace sf {
 // Register target of five waves per SIMD (80 VGPRs, no spills): more resident workgroups
 // hide the write latency; measured faster for p = 1 and 3, slower for p = 2 (kept at the
 // compiler's default there), no effect for p >= 4.
-template <int N, int NQ, int FORM, typename IO, int C, int NT, int R>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(N == 3 ? 1 : 5, 8)))
+// MODE: SF_FP64, or SF_BF16 / SF_FP16 / SF_BF16X3 for the final (q0) contraction on the
+// matrix cores with FP32 accumulation (stage 1 and phase A stay FP64).
+template <int N, int NQ, int FORM, typename IO, int C, int NT, int R, int MODE = SF_FP64>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(N == 3 || MODE != SF_FP64 ? 1 : 5, 8)))
     matrix_q_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                     IO *__restrict__ A, const double *__restrict__ tab, int *__restrict__ err)
 {
     __shared__ double smem[MatrixQSmem<N, NQ, FORM, C>::doubles];
-    matrix_q_body<N, NQ, FORM, IO, C, NT, R>(int64_t(blockIdx.x) * C, ncells, vert, kappa, A, 0, tab, err, smem);
+    matrix_q_body<N, NQ, FORM, IO, C, NT, R, MODE>(int64_t(blockIdx.x) * C, ncells, vert, kappa, A, 0, tab, err,
+                                                    smem);
 }
 
 // clears the off-diagonal blocks' buffer before the vector element's diagonal
@@ -49,7 +53,7 @@ template <typename IO> __global__ void matrix_clear_kernel(IO *A, int64_t n)
 
 namespace {
 
-template <int N, int FORM, typename IO, int R>
+template <int N, int FORM, typename IO, int R, int MODE = SF_FP64>
 int launch_one(const LaunchArgs &a)
 {
     constexpr int N3 = N * N * N;
@@ -64,15 +68,34 @@ int launch_one(const LaunchArgs &a)
         hipLaunchKernelGGL(matrix_clear_kernel<IO>, dim3(unsigned(blocks)), dim3(256), 0, a.stream,
                            static_cast<IO *>(a.A), n);
     }
-    hipLaunchKernelGGL((matrix_q_kernel<N, N, FORM, IO, C, NT, R>), dim3(unsigned(groups)), dim3(NT), 0, a.stream,
+    hipLaunchKernelGGL((matrix_q_kernel<N, N, FORM, IO, C, NT, R, MODE>), dim3(unsigned(groups)), dim3(NT), 0, a.stream,
                        a.ncells, a.vert, static_cast<const IO *>(a.kappa), static_cast<IO *>(a.A), a.tab64, a.err);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+template <int N, int FORM, typename IO>
+int launch_mixed(const LaunchArgs &a)
+{
+    switch (a.precision) {
+    case SF_BF16: return launch_one<N, FORM, IO, 1, SF_BF16>(a);
+    case SF_FP16: return launch_one<N, FORM, IO, 1, SF_FP16>(a);
+    case SF_BF16X3: return launch_one<N, FORM, IO, 1, SF_BF16X3>(a);
+    default: return SF_ERR_UNSUPPORTED;
+    }
 }
 
 template <int N, int R>
 int launch_nr(const LaunchArgs &a)
 {
-    if (a.precision != SF_FP64) return SF_ERR_UNSUPPORTED;
+    if (a.precision != SF_FP64) {
+        // lower-precision final contraction: scalar Q_p / dQ_p, box cells
+        if (R != 1) return SF_ERR_UNSUPPORTED;
+        if (a.form == SF_MASS)
+            return a.io == SF_F64 ? launch_mixed<N, SF_MASS, double>(a) : launch_mixed<N, SF_MASS, float>(a);
+        if (a.form == SF_LAPLACE)
+            return a.io == SF_F64 ? launch_mixed<N, SF_LAPLACE, double>(a) : launch_mixed<N, SF_LAPLACE, float>(a);
+        return SF_ERR_UNSUPPORTED;
+    }
     if (a.form == SF_MASS)
         return a.io == SF_F64 ? launch_one<N, SF_MASS, double, R>(a) : launch_one<N, SF_MASS, float, R>(a);
     if (a.form == SF_LAPLACE)

@@ -26,8 +26,10 @@
 
 namespace sf {
 
+// Register target: four waves per SIMD for the single-term modes; three for BF16X3,
+// whose split operands need more registers (at four it spilled to scratch)
 template <int N, int NQ, int FORM, bool COLL, int MODE, typename IO, int C, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == SF_BF16X3 ? 3 : 4, 8)))
     action_mixed_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                         const IO *__restrict__ u, IO *__restrict__ y, const double *__restrict__ tab64,
                         const uint16_t *__restrict__ mix, int *__restrict__ err)

@@ -1,6 +1,6 @@
 // Element matrices of the linearised Saint Venant-Kirchhoff residual on the
 // vector Q_p element (the left-hand side of the hyperelastic model in the
-// paper's evaluation), FP64, p <= 4, on gfx950.
+// paper's evaluation), FP64, p <= 8, on gfx950.
 //
 // Argument factorisation (Sec. 3.2): with the tangent modulus Amod of P at
 // the linearisation point,
@@ -30,9 +30,13 @@
 namespace sf {
 
 // threads per workgroup: one per column j of a block row, (p+1)^3 rounded up to a
-// wave, for p <= 3; 256 for p = 4, where the first two stages' extra threads pay more
-// than the idle lanes of the last one cost (measured)
-__host__ __device__ constexpr int svk_matrix_nt(int n) { return n <= 4 ? (n * n * n + 63) / 64 * 64 : 256; }
+// wave, for p <= 3; 256 for p = 4..5, where the first two stages' extra threads pay more
+// than the idle lanes of the last one cost (measured); 512 from p = 6 on, where the
+// LDS holds one or two workgroups per CU and more waves hide the write latency
+__host__ __device__ constexpr int svk_matrix_nt(int n) { return n <= 4 ? (n * n * n + 63) / 64 * 64 : (n <= 6 ? 256 : 512); }
+// phase-A buffers: two (the next phase A overlaps this phase B) while the LDS holds
+// 29 n^3 doubles, one (and a barrier) above
+__host__ __device__ constexpr int svk_t2_buffers(int n) { return 29 * n * n * n * 8 <= 150 * 1024 ? 2 : 1; }
 
 template <int N, bool TRI>
 __global__ void __launch_bounds__(svk_matrix_nt(N))
@@ -51,7 +55,8 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
     __shared__ double sGeo[34];        // vertices (24), G (9), |det J|
     __shared__ double sK[9 * N3];      // K_{dd'} at the points, product p = 3 d + d'
     __shared__ double sT1[9 * T1SZ];   // stage 1, one i2-slice per product
-    __shared__ double sT2[2 * 4 * T2SZ]; // phase A, four groups, two buffers
+    constexpr int NB2 = svk_t2_buffers(N);
+    __shared__ double sT2[NB2 * 4 * T2SZ]; // phase A, four groups, one or two buffers
 
     const int64_t cell = int64_t(blockIdx.x) / 9;
     const int blk = int(blockIdx.x - cell * 9), cr = blk / 3, cc = blk - cr * 3; // block (test cr, trial cc)
@@ -85,10 +90,10 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
     }
 
     // ---- reference gradient of u0 at the points, sum-factorised one axis at a time:
-    // axis 2 with B and D (sT2: [c][B|D][i0][i1][q2]); axis 1 (sT1: [c][BB|DB|BD][i0][q1][q2],
-    // the first letter the axis-1 table); axis 0 into sK ([c][d][q]: d0 = D0 BB, d1 = B0 DB,
-    // d2 = B0 BD).  The pointwise stage below reads a point's nine values and then
-    // overwrites the same point of sK with the coefficients.
+    // axis 2 with B and D (sT1: [c][B|D][i0][i1][q2]); axis 1 (sK: [c][BB|DB|BD][i0][q1][q2],
+    // the first letter the axis-1 table); axis 0 into sT1 ([c][d][q]: d0 = D0 BB, d1 = B0 DB,
+    // d2 = B0 BD).  The pointwise stage below reads a point's nine values from sT1 and
+    // writes the coefficients to sK.
     for (int t = tid; t < 6 * N3; t += NT) {
         const int cs = t / N3, r = t - cs * N3, c = cs >> 1;
         const int i01 = r / N, q2 = r - i01 * N;
@@ -97,29 +102,29 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
         double acc = 0.0;
 #pragma unroll
         for (int i2 = 0; i2 < N; ++i2) acc = fma(X[q2 * N + i2], uc[i2], acc);
-        sT2[t] = acc;
+        sT1[t] = acc;
     }
     __syncthreads();
     for (int t = tid; t < 9 * N3; t += NT) {
         const int ck = t / N3, r = t - ck * N3, c = ck / 3, k = ck - c * 3;
         const int i0 = r / N2, q1 = (r / N) % N, q2 = r % N;
         const double *X = k == 1 ? sD : sB;                                   // axis-1 table
-        const double *src = sT2 + (2 * c + (k == 2 ? 1 : 0)) * N3 + i0 * N2 + q2; // B or D on axis 2
+        const double *src = sT1 + (2 * c + (k == 2 ? 1 : 0)) * N3 + i0 * N2 + q2; // B or D on axis 2
         double acc = 0.0;
 #pragma unroll
         for (int i1 = 0; i1 < N; ++i1) acc = fma(X[q1 * N + i1], src[i1 * N], acc);
-        sT1[t] = acc;
+        sK[t] = acc;
     }
     __syncthreads();
     for (int t = tid; t < 9 * N3; t += NT) {
         const int cd = t / N3, q = t - cd * N3, c = cd / 3, d = cd - c * 3;
         const int q0 = q / N2, q12 = q - q0 * N2;
         const double *X = d == 0 ? sD : sB; // axis-0 table
-        const double *src = sT1 + (3 * c + d) * N3 + q12;
+        const double *src = sK + (3 * c + d) * N3 + q12;
         double acc = 0.0;
 #pragma unroll
         for (int i0 = 0; i0 < N; ++i0) acc = fma(X[q0 * N + i0], src[i0 * N2], acc);
-        sK[t] = acc;
+        sT1[t] = acc;
     }
     __syncthreads();
 
@@ -145,7 +150,7 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) gu[c][d] = sK[(3 * c + d) * N3 + q];
+            for (int d = 0; d < 3; ++d) gu[c][d] = sT1[(3 * c + d) * N3 + q];
         double F[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -208,7 +213,7 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
         }
         __syncthreads();
         for (int i1 = 0; i1 < N; ++i1) {
-            double *T2 = sT2 + ((i2 * N + i1) & 1) * 4 * T2SZ;
+            double *T2 = sT2 + (NB2 == 2 ? ((i2 * N + i1) & 1) : 0) * 4 * T2SZ;
             // phase A: T2_g[q0][j1][j2] = sum over products p of group g of
             //          sum_q1 X1_p[q1][i1] Y1_p[q1][j1] T1_p[q0][q1][j2]
             for (int t = tid; t < 4 * N3; t += NT) {
@@ -242,7 +247,9 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
                 for (int g = 0; g < 4; ++g) {
                     const double *X = (g >> 1) ? sD : sB;
                     const double *Y = (g & 1) ? sD : sB;
-#pragma unroll
+                    // at n >= 8 a rolled q0 loop: unrolled, the compiler keeps every table
+                    // entry of the sweep in registers across the column loop and spills
+#pragma unroll(N >= 8 ? 1 : N)
                     for (int q0 = 0; q0 < N; ++q0) {
                         const double yt = Y[q0 * N + j0] * T2[g * T2SZ + q0 * N2 + j12];
 #pragma unroll
@@ -252,8 +259,10 @@ __global__ void __launch_bounds__(svk_matrix_nt(N))
 #pragma unroll
                 for (int i0 = 0; i0 < N; ++i0) A[rowbase + int64_t(i0 * N2 + i1 * N + i2) * ND + j] = out[i0];
             }
-            // the next phase A writes the other T2 buffer; stage 1 of the next slice is
-            // separated from this phase B's T1-free reads by the barrier after phase A
+            // with two buffers the next phase A writes the other one; stage 1 of the next
+            // slice is separated from this phase B's T1-free reads by the barrier after
+            // phase A; with one buffer the next phase A waits for this phase B
+            if constexpr (NB2 == 1) __syncthreads();
         }
         __syncthreads(); // the next stage 1 overwrites T1 read by the last phase A
     }
@@ -282,6 +291,10 @@ int launch_matrix_svk(const LaunchArgs &a)
     case 3: return a.trilinear ? launch_svk_matrix_n<3, true>(a) : launch_svk_matrix_n<3, false>(a);
     case 4: return a.trilinear ? launch_svk_matrix_n<4, true>(a) : launch_svk_matrix_n<4, false>(a);
     case 5: return a.trilinear ? launch_svk_matrix_n<5, true>(a) : launch_svk_matrix_n<5, false>(a);
+    case 6: return a.trilinear ? launch_svk_matrix_n<6, true>(a) : launch_svk_matrix_n<6, false>(a);
+    case 7: return a.trilinear ? launch_svk_matrix_n<7, true>(a) : launch_svk_matrix_n<7, false>(a);
+    case 8: return a.trilinear ? launch_svk_matrix_n<8, true>(a) : launch_svk_matrix_n<8, false>(a);
+    case 9: return a.trilinear ? launch_svk_matrix_n<9, true>(a) : launch_svk_matrix_n<9, false>(a);
     default: return SF_ERR_UNSUPPORTED;
     }
 }

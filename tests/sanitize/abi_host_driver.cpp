@@ -173,8 +173,14 @@ int main()
         CHECK(assemble_action(&ctx, &lo32, 4, dummy, nullptr, dummy, dummy + 1, nullptr) == SF_ERR_UNSUPPORTED);
         sf_op mat{SF_Q, 3, SF_LAPLACE, 0, SF_BF16, SF_F64, 1.0, 1.0};
         CHECK(assemble_element_matrix(&ctx, &mat, 4, dummy, nullptr, dummy, nullptr) == SF_ERR_UNSUPPORTED);
-        sf_op svk5{SF_Q, 5, SF_SVK, 0, SF_FP64, SF_F64, 1.0, 1.0};
-        CHECK(assemble_element_matrix(&ctx, &svk5, 4, dummy, nullptr, dummy, nullptr) == SF_ERR_UNSUPPORTED);
+        sf_op svk32{SF_Q, 5, SF_SVK, 0, SF_FP32, SF_F64, 1.0, 1.0};
+        CHECK(assemble_element_matrix(&ctx, &svk32, 4, dummy, nullptr, dummy, nullptr) == SF_ERR_UNSUPPORTED);
+        sf_op res2{SF_Q, 2, SF_SVK_RESIDUAL, 0, SF_FP64, SF_F64, 1.0, 1.0};
+        CHECK(assemble_element_matrix(&ctx, &res2, 4, dummy, nullptr, dummy, nullptr) == SF_ERR_UNSUPPORTED);
+        sf_op gll16{SF_QGLL, 3, SF_LAPLACE, 0, SF_FP16, SF_F64, 1.0, 1.0};
+        CHECK(sf_set_geometry(&ctx, SF_GEOM_BOX) == SF_OK);
+        CHECK(assemble_element_matrix(&ctx, &gll16, 4, dummy, nullptr, dummy, nullptr) == SF_ERR_UNSUPPORTED);
+        CHECK(sf_set_geometry(&ctx, SF_GEOM_TRILINEAR) == SF_OK);
         CHECK(assemble_element_matrix(&ctx, &op, 4, dummy, dummy, dummy, nullptr) == SF_ERR_ARG);
         sf_op lowp{SF_Q, 3, SF_LAPLACE, 0, SF_BF16, SF_F64, 1.0, 1.0};
         CHECK(assemble_action_box_noalloc(&ctx, &lowp, 4, dummy, nullptr, dummy, dummy + 1, nullptr) ==

@@ -24,11 +24,21 @@ def ctx(lib):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_box(lib):
+    """A context declared SF_GEOM_BOX: the batch's FP64 actions run the box-cell body."""
+    c = sf.Context(0)
+    sf.sf_set_geometry(c, "box")
+    yield c
+    c.close()
+
+
 def make_jobs(seed=5):
     """A mixed batch: (kind, p, grid) with kind in act_fp64 / act_bf16 / act_bf16x3 / mat."""
     spec = [("act", "fp64", 2, (5, 4, 6)), ("act", "fp64", 8, (3, 3, 4)), ("mat", "fp64", 3, (2, 2, 3)),
             ("act", "bf16x3", 5, (4, 4, 3)), ("act", "bf16", 4, (3, 5, 2)), ("mat", "fp64", 7, (1, 1, 3)),
-            ("act", "fp64", 1, (7, 7, 7)), ("act", "bf16x3", 8, (2, 2, 3)), ("mat", "fp64", 8, (1, 1, 2))]
+            ("act", "fp64", 1, (7, 7, 7)), ("act", "bf16x3", 8, (2, 2, 3)), ("mat", "fp64", 8, (1, 1, 2)),
+            ("mat", "bf16", 4, (2, 2, 2)), ("mat", "bf16x3", 6, (1, 2, 2))]
     jobs = []
     for i, (kind, prec, p, grid) in enumerate(spec):
         V = synth.box_mesh(*grid, 100 + i)
@@ -58,8 +68,10 @@ def sf_jobs(jobs):
     return out
 
 
-def standalone(ctx, r):
+def standalone(ctx, r, ctx_box=None):
     op = sf.make_op("Q", r["p"], "LAPLACE", precision=r["prec"])
+    if r["kind"] == "mat" and r["prec"] != "fp64":
+        ctx = ctx_box  # lower-precision element matrices: the box-cell kernel
     if r["kind"] == "act":
         y = empty((r["n"], r["nd"]), np.float64)
         sf.assemble_action(ctx, op, r["n"], r["dV"], r["dk"], r["du"], y)
@@ -69,10 +81,12 @@ def standalone(ctx, r):
     return host(A)
 
 
-def test_batch_graph_replays_match_standalone_and_oracle(ctx):
+@pytest.mark.parametrize("geom", ["affine", "box"])
+def test_batch_graph_replays_match_standalone_and_oracle(ctx, ctx_box, geom):
     import torch
+    ctx = ctx_box if geom == "box" else ctx
     jobs = make_jobs()
-    refs = [standalone(ctx, r) for r in jobs]
+    refs = [standalone(ctx, r, ctx_box) for r in jobs]
     batch = sf.Batch(ctx, sf_jobs(jobs))
     ntiles, nwg = batch.info()
     assert ntiles >= len(jobs) and nwg >= 1
@@ -91,7 +105,7 @@ def test_batch_graph_replays_match_standalone_and_oracle(ctx):
     # oracle on a sample of cells of every job
     for r, ref in zip(jobs, refs):
         idx = np.unique(np.linspace(0, r["n"] - 1, 4).astype(int))
-        tol = {"fp64": 1e-12, "bf16x3": 1e-6, "bf16": 1.5e-1}[r["prec"]]
+        tol = {"fp64": 1e-12, "bf16x3": 1e-6, "bf16": 1.5e-1 if r["kind"] == "act" else 2e-2}[r["prec"]]
         if r["kind"] == "act":
             o = oracle.action("Q", r["p"], "LAPLACE", r["V"][idx], r["u"][idx], kappa=r["kap"][idx])
             assert rel_l2(ref[idx], o) <= tol
@@ -147,3 +161,22 @@ def test_autotune_cache_roundtrip(ctx):
         sf.sf_load_tuning(c2, path)
         assert sf.sf_tuned_variant(c2, op) == v
         c2.close()
+        # every tunable class of the op is recorded: batched action tiles, batched
+        # element-matrix tiles, the stand-alone box-cell kernel
+        for what in ("batch", "batch_matrix", "standalone"):
+            assert "gfx950|fam0|p3|form1|nq4|prec0|io0|" + what in data, what
+        # classes with only some of the choices: the mass form and FP32 storage (stand-alone
+        # only), BF16 contractions (batched tiles only), the collocated family
+        for op2, keys in ((sf.make_op("Q", 3, "MASS"), ["standalone"]),
+                          (sf.make_op("DQ", 5, "LAPLACE", precision="fp32", io="f32"), ["standalone"]),
+                          (sf.make_op("Q", 4, "LAPLACE", precision="bf16"), ["batch"]),
+                          (sf.make_op("QGLL", 6, "LAPLACE"), ["standalone"])):
+            sf.sf_autotune(ctx, op2, 20000, path)
+            data = json.load(open(path))
+            for what in keys:
+                key = "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|%s" % (
+                    op2.family, op2.degree, op2.form, op2.degree + 1, op2.precision, op2.io_dtype, what)
+                assert key in data and 0 <= data[key] < 6, key
+        with pytest.raises(sf.SfError) as e:
+            sf.sf_autotune(ctx, sf.make_op("NCF", 2, "HDIV"), 1000, path)
+        assert e.value.code == sf.SF_ERR_UNSUPPORTED

@@ -69,3 +69,52 @@ def test_mixed_unsupported_for_vector_families(ctx):
     with pytest.raises(sf.SfError) as e:
         sf.assemble_action(ctx, op, 2, dev(V), None, u, y)
     assert e.value.code == sf.SF_ERR_UNSUPPORTED
+
+
+@pytest.fixture(scope="module")
+def ctx_box(lib):
+    c = sf.Context(0)
+    sf.sf_set_geometry(c, "box")
+    yield c
+    c.close()
+
+
+# only the final (q0) contraction of the element matrix runs in the lower precision:
+# one rounding of each operand (2^-9 BF16, 2^-12 FP16 relative), about 2^-24 for BF16X3
+MAT_BOUND = {"bf16x3": 1e-6, "fp16": 5e-3, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16", "bf16"])
+@pytest.mark.parametrize("family,form", [("Q", "LAPLACE"), ("Q", "MASS"), ("DQ", "LAPLACE")])
+@pytest.mark.parametrize("p", range(1, 9))
+def test_mixed_element_matrix_error(ctx_box, mode, family, form, p):
+    """Element matrices with the final contraction on MFMA (FP32 accumulation) on box
+    cells, against the FP64 oracle; FP32 storage of the output for one case each."""
+    n = {1: 45, 2: 14, 3: 9, 4: 5, 5: 3, 6: 2, 7: 2, 8: 2}[p]
+    V = synth.box_mesh(1, 1, n, 210 + p)
+    nd = (p + 1) ** 3
+    kap = synth.kappa(n, nd, 210 + p)
+    io = "f32" if (p == 3 and family == "Q") else "f64"
+    npio = np.float32 if io == "f32" else np.float64
+    op = sf.make_op(family, p, form, precision=mode, io=io)
+    A = empty((n, nd, nd), npio)
+    A.fill_(np.nan)
+    sf.assemble_element_matrix(ctx_box, op, n, dev(V), dev(kap.astype(npio)), A)
+    assert sf.sf_check_errors(ctx_box) == 0
+    ref = oracle.element_matrix(family, p, form, V, kappa=kap.astype(npio).astype(np.float64))
+    got = host(A)
+    assert np.isfinite(got).all()
+    err = rel_l2(got, ref)
+    print("mixed matrix", mode, family, form, p, "rel_l2 %.3e" % err, flush=True)
+    assert err <= max(MAT_BOUND[mode], 2e-7 if io == "f32" else 0.0), err
+
+
+def test_mixed_element_matrix_rejections(ctx, ctx_box):
+    V = dev(synth.box_mesh(1, 1, 2, 220))
+    A = empty((2, 27, 27), np.float64)
+    for c, op in ((ctx, sf.make_op("Q", 2, "LAPLACE", precision="bf16")),          # not a box context
+                  (ctx_box, sf.make_op("QGLL", 2, "LAPLACE", precision="bf16")),   # collocated family
+                  (ctx_box, sf.make_op("Q", 2, "LAPLACE", precision="fp32"))):     # no FP32 matrix kernel
+        with pytest.raises(sf.SfError) as e:
+            sf.assemble_element_matrix(c, op, 2, V, None, A)
+        assert e.value.code == sf.SF_ERR_UNSUPPORTED
