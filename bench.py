@@ -243,7 +243,8 @@ def tuning_classes(sf, degrees, mixed_degrees, legs):
     """Every op class the run times whose kernel choice the autotuner makes, with the
     choice keys it records: the headline (stand-alone box kernel, batched tiles of
     actions and element matrices), the mass and collocated legs, the FP32 rows of the
-    mixed-precision leg and the batched BF16 / BF16x3 tiles."""
+    mixed-precision leg, the batched BF16 / BF16x3 tiles and the H(div) / H(curl)
+    actions."""
     out = []
     for p in degrees:
         op = sf.make_op("Q", p, "LAPLACE")
@@ -263,6 +264,12 @@ def tuning_classes(sf, degrees, mixed_degrees, legs):
             for prec in ("bf16", "bf16x3"):
                 op = sf.make_op("Q", p, "LAPLACE", precision=prec)
                 out.append((op, [tune_key(op, "batch")]))
+    if "vec" in legs:
+        for fam, form in (("NCF", "HDIV"), ("NCE", "HCURL")):
+            for io in ("f64", "f32"):
+                for k in range(1, 7):
+                    op = sf.make_op(fam, k, form, io=io)
+                    out.append((op, [tune_key(op, "standalone")]))
     return out
 
 

@@ -153,7 +153,11 @@ const char *sf_status_string(int status);
  * the general kernel for that op (variant 3 below), which stays exact and
  * raises nothing; the mass action needs only |det J| and stays exact on any
  * affine cell.  Element matrices of SF_Q / SF_VQ then use the box kernel
- * (see assemble_element_matrix); the H(div) / H(curl) kernels do not change.
+ * (see assemble_element_matrix).  The SF_NCF / SF_NCE actions use diagonal
+ * Piola factors (h_c^2 / |J|, |J| / h_c^2) with the pointwise stage fused into
+ * the contractions; a cell with off-diagonal J raises SF_FLAG_NONBOX and only
+ * the diagonal factors are applied to it (unless the autotuner picked the
+ * general kernel, variant 2 of that class, which stays exact).
  * Returns SF_ERR_ARG for an unknown value. */
 #define SF_GEOM_AFFINE 0
 #define SF_GEOM_BOX 1
@@ -363,7 +367,12 @@ int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
  *     SF_GEOM_BOX (0: prefetch of the next cell group, >= 3 workgroups per
  *     CU; 1: no prefetch, >= 4; 2: prefetch, >= 2; 3: the general
  *     three-tensor kernel that SF_GEOM_AFFINE uses; 4 and 5: 128-thread
- *     workgroups with and without prefetch).
+ *     workgroups with and without prefetch);
+ *   "standalone" (SF_NCF, SF_NCE; SF_FP64 or SF_FP32; either storage): the
+ *     H(div) / H(curl) action kernel used under SF_GEOM_BOX (0: diagonal
+ *     Piola factors with the pointwise stage fused into the contractions;
+ *     1: one cell group per workgroup; 2: the persistent kernel with full
+ *     per-cell Piola factors that SF_GEOM_AFFINE uses).
  * When cache_json_path is non-NULL the choices are merged into that JSON
  * file, keyed by architecture, family, degree, form, nq1, precision, io dtype
  * and the choice name.  Later calls with the same key use the winners.

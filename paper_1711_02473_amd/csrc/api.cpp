@@ -142,6 +142,30 @@ bool pack_eo(std::vector<double> &h, int src, int dst, int n, bool skew)
     return true;
 }
 
+// The same packing for a rectangular no x ni matrix with M[no-1-q][ni-1-i] = s M[q][i]:
+// rows q < no/2 hold the ni/2 half-sums, M[q][ni/2] when ni is odd, then the ni/2
+// half-differences; for odd no the middle row's first ni/2 + ni%2 entries follow
+// (the output equals pack_eo's when no == ni).  Returns false if M lacks the symmetry.
+bool pack_eo_rect(std::vector<double> &h, int src, int dst, int no, int ni, bool skew)
+{
+    const double s = skew ? -1.0 : 1.0;
+    double scale = 0.0;
+    for (int k = 0; k < no * ni; ++k) scale = std::max(scale, std::fabs(h[src + k]));
+    auto M = [&](int q, int i) { return h[src + size_t(q) * ni + i]; };
+    for (int q = 0; q < no; ++q)
+        for (int i = 0; i < ni; ++i)
+            if (std::fabs(M(no - 1 - q, ni - 1 - i) - s * M(q, i)) > 1e-12 * scale) return false;
+    const int hi = ni / 2, oi = ni % 2, ho = no / 2, rw = 2 * hi + oi;
+    for (int q = 0; q < ho; ++q) {
+        for (int i = 0; i < hi; ++i) h[dst + q * rw + i] = 0.5 * (M(q, i) + M(q, ni - 1 - i));
+        if (oi) h[dst + q * rw + hi] = M(q, hi);
+        for (int i = 0; i < hi; ++i) h[dst + q * rw + hi + oi + i] = 0.5 * (M(q, i) - M(q, ni - 1 - i));
+    }
+    if (no % 2)
+        for (int i = 0; i < hi + oi; ++i) h[dst + ho * rw + i] = M(ho, i);
+    return true;
+}
+
 } // namespace
 
 namespace sf {
@@ -180,6 +204,18 @@ int host_table_block(int family, int n0, int n1, int nq1, std::vector<double> &h
         const bool ok = pack_eo(h, L.B0(), L.BEO(), nq1, false) && pack_eo(h, L.B0T(), L.BTEO(), nq1, false) &&
                         pack_eo(h, L.Dh(), L.DhEO(), nq1, true) && pack_eo(h, L.DhT(), L.DhTEO(), nq1, true);
         if (!ok) return SF_ERR_UNSUPPORTED;
+    }
+    if (n1 > 0) {
+        // enriched elements: D0 (skew), B1 (node sets GLL_n0 / GL_n1, points GL) and their
+        // transposes in even-odd form; the 3-D weight products
+        const bool ok = pack_eo_rect(h, L.D0(), L.D0EO(), nq1, n0, true) &&
+                        pack_eo_rect(h, L.D0T(), L.D0TEO(), n0, nq1, true) &&
+                        pack_eo_rect(h, L.B1(), L.B1EO(), nq1, n1, false) &&
+                        pack_eo_rect(h, L.B1T(), L.B1TEO(), n1, nq1, false);
+        if (!ok) return SF_ERR_UNSUPPORTED;
+        for (int a = 0; a < nq1; ++a)
+            for (int b = 0; b < nq1; ++b)
+                for (int c = 0; c < nq1; ++c) h[L.W3() + (a * nq1 + b) * nq1 + c] = wq[a] * wq[b] * wq[c];
     }
     return SF_OK;
 }
@@ -423,6 +459,11 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
         return launch_action_q(a);
     }
     a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
+    a.box = ctx->geometry == SF_GEOM_BOX;
+    // variant 0: the fused box-cell kernel on box contexts, the persistent affine kernel
+    // otherwise; 1: one group per workgroup; 2: the persistent affine kernel.  Untuned NCE_6
+    // on boxes takes 2 (the fused form's registers spill at that degree).
+    a.variant = tuned_variant_of(ctx, op, "standalone", a.box && op->family == SF_NCE && op->degree == 6 ? 2 : 0);
     return launch_action_vec(a);
 }
 

@@ -511,7 +511,11 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
     const bool tune_matrix = tune_batch && op->precision == SF_FP64;
     const bool tune_sa = scalar && (op->form == SF_MASS || op->form == SF_LAPLACE) &&
                          (op->precision == SF_FP64 || op->precision == SF_FP32);
-    if (!tune_batch && !tune_sa) return SF_ERR_UNSUPPORTED;
+    // H(div) / H(curl) actions on box cells: fused box-cell kernel (0), one group per
+    // workgroup (1) or the persistent affine kernel (2)
+    const bool tune_vec = (op->family == SF_NCF || op->family == SF_NCE) &&
+                          (op->precision == SF_FP64 || op->precision == SF_FP32);
+    if (!tune_batch && !tune_sa && !tune_vec) return SF_ERR_UNSUPPORTED;
     const int64_t nc = std::min<int64_t>(ncells_hint, 1 << 20);
     const size_t esz = op->io_dtype == SF_F32 ? 4 : 8;
     // element matrices of at most 512 MiB for the matrix tiles
@@ -592,7 +596,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
             }
         }
     };
-    int best = 2, best_mat = 0, best_sa = 0;
+    int best = 2, best_mat = 0, best_sa = 0, best_vec = 0;
     if (tune_batch) tune_tiles(false, best);
     if (tune_matrix) tune_tiles(true, best_mat);
     if (ok && tune_sa) {
@@ -621,6 +625,32 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
             }
         }
     }
+    if (ok && tune_vec) {
+        LaunchArgs a;
+        ok = ensure_tables(ctx, op, a) == SF_OK;
+        float best_vec_ms = 1e30f;
+        const int order[3] = {0, 2, 1};
+        for (int i = 0; ok && i < 3; ++i) {
+            const int v = order[i];
+            a.ncells = nc;
+            a.vert = vert;
+            a.kappa = nullptr;
+            a.u = u;
+            a.y = y;
+            a.stream = s;
+            a.box = true;
+            a.trilinear = false;
+            a.variant = v;
+            const float t = time3([&] { return launch_action_vec(a) == SF_OK; });
+            if (!ok)
+                std::fprintf(stderr, "sf_autotune: timing the H(div)/H(curl) variant %d failed (%s)\n", v,
+                             hipGetErrorString(hipGetLastError()));
+            if (ok && t < 0.98f * best_vec_ms) {
+                best_vec_ms = t;
+                best_vec = v;
+            }
+        }
+    }
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -635,6 +665,7 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
     if (tune_batch) got[tune_key(op, "batch")] = best;
     if (tune_matrix) got[tune_key(op, "batch_matrix")] = best_mat;
     if (tune_sa) got[tune_key(op, "standalone")] = best_sa;
+    if (tune_vec) got[tune_key(op, "standalone")] = best_vec;
     for (auto &kv : got) ctx->tuned[kv.first] = kv.second;
     if (cache_json_path) {
         auto m = read_json(cache_json_path);

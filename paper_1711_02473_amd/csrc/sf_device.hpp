@@ -160,6 +160,74 @@ __device__ __forceinline__ void apply_eo(const T *M, const T (&x)[N], T (&y)[N])
     }
 }
 
+// Even-odd application of a rectangular NO x NI matrix with M[NO-1-q][NI-1-i] =
+// s M[q][i] (s = -1 when SKEW), packed as pack_eo_rect builds it: rows q < NO/2
+// give E (half-sums against x_e, plus the middle column against x[NI/2] for odd
+// NI) and O (half-differences against x_o), y[q] = E + O, y[NO-1-q] = s (E - O);
+// the middle row of odd NO uses x_e and the middle entry (x_o when SKEW).  NI = 1
+// or NO = 1 are allowed.  About NO NI / 2 + NI + NO operations instead of NO NI.
+template <int NO, int NI, bool SKEW, bool ACC, typename T>
+__device__ __forceinline__ void apply_eo_rect(const T *M, const T (&x)[NI], T (&y)[NO])
+{
+    constexpr int hi = NI / 2, oi = NI % 2, ho = NO / 2, oo = NO % 2, RW = 2 * hi + oi;
+    T xe[hi > 0 ? hi : 1], xo[hi > 0 ? hi : 1];
+#pragma unroll
+    for (int i = 0; i < hi; ++i) {
+        xe[i] = x[i] + x[NI - 1 - i];
+        xo[i] = x[i] - x[NI - 1 - i];
+    }
+#pragma unroll
+    for (int q = 0; q < ho; ++q) {
+        cptr<T> m = (q >= 2) ? fresh_after(M, y[q - 2]) : fresh(M);
+        T e;
+        if constexpr (hi > 0) {
+            e = T(m[q * RW]) * xe[0];
+#pragma unroll
+            for (int i = 1; i < hi; ++i) e = fmadd(T(m[q * RW + i]), xe[i], e);
+            if constexpr (oi) e = fmadd(T(m[q * RW + hi]), x[hi], e);
+        } else {
+            e = T(m[q * RW]) * x[0];
+        }
+        T lo = e, up = SKEW ? -e : e;
+        if constexpr (hi > 0) {
+            T o = T(m[q * RW + hi + oi]) * xo[0];
+#pragma unroll
+            for (int i = 1; i < hi; ++i) o = fmadd(T(m[q * RW + hi + oi + i]), xo[i], o);
+            lo = e + o;
+            up = SKEW ? o - e : e - o;
+        }
+        if constexpr (ACC) {
+            y[q] += lo;
+            y[NO - 1 - q] += up;
+        } else {
+            y[q] = lo;
+            y[NO - 1 - q] = up;
+        }
+    }
+    if constexpr (oo) {
+        cptr<T> m = (ho >= 1) ? fresh_after(M, y[ho - 1]) : fresh(M);
+        T a = T(0);
+        if constexpr (SKEW) {
+            if constexpr (hi > 0) {
+                a = T(m[ho * RW]) * xo[0];
+#pragma unroll
+                for (int i = 1; i < hi; ++i) a = fmadd(T(m[ho * RW + i]), xo[i], a);
+            }
+        } else {
+            if constexpr (hi > 0) {
+                a = T(m[ho * RW]) * xe[0];
+#pragma unroll
+                for (int i = 1; i < hi; ++i) a = fmadd(T(m[ho * RW + i]), xe[i], a);
+                if constexpr (oi) a = fmadd(T(m[ho * RW + hi]), x[hi], a);
+            } else {
+                a = T(m[ho * RW]) * x[0];
+            }
+        }
+        if constexpr (ACC) y[ho] += a;
+        else y[ho] = a;
+    }
+}
+
 // This thread's share (slots t = threadIdx.x + k NT < C E) of a group's
 // cell-major rows of E entries, loaded in one batch so that the loads
 // overlap; `fill` for padding cells, empty slots or a NULL array.

@@ -53,7 +53,19 @@ struct TabLayout {
     __host__ __device__ constexpr int DhEO() const { return BTEO() + eo_len(nq); }
     __host__ __device__ constexpr int DhTEO() const { return DhEO() + eo_len(nq); }
     __host__ __device__ constexpr int XQ() const { return DhTEO() + eo_len(nq); } // quadrature points
-    __host__ __device__ constexpr int size() const { return XQ() + nq; }
+    // Enriched (two-factor) elements only, empty when n1 == 0: even-odd packed forms of
+    // D0, D0^T (skew) and of the rectangular B1, B1^T, and the products w_q0 w_q1 w_q2
+    // of the 1-D weights at the n_q^3 points (index (q0 nq + q1) nq + q2).
+    __host__ __device__ static constexpr int eo_len2(int no, int ni)
+    {
+        return (no / 2) * (2 * (ni / 2) + ni % 2) + (no % 2) * (ni / 2 + ni % 2);
+    }
+    __host__ __device__ constexpr int D0EO() const { return XQ() + nq; }
+    __host__ __device__ constexpr int D0TEO() const { return D0EO() + (n1 > 0 ? eo_len2(nq, n0) : 0); }
+    __host__ __device__ constexpr int B1EO() const { return D0TEO() + (n1 > 0 ? eo_len2(n0, nq) : 0); }
+    __host__ __device__ constexpr int B1TEO() const { return B1EO() + (n1 > 0 ? eo_len2(nq, n1) : 0); }
+    __host__ __device__ constexpr int W3() const { return B1TEO() + (n1 > 0 ? eo_len2(n1, nq) : 0); }
+    __host__ __device__ constexpr int size() const { return W3() + (n1 > 0 ? nq * nq * nq : 0); }
 };
 
 // Tables split into three bf16 terms (hi, mid, lo) and single fp16 / bf16
@@ -86,6 +98,8 @@ struct LaunchArgs {
     int *sched = nullptr;
     // cells are general trilinear hexahedra: geometry per quadrature point
     bool trilinear = false;
+    // cells are axis-aligned boxes (the context's geometry): diagonal geometric factors
+    bool box = false;
 };
 
 // ring of counter slots per context: consecutive launches take consecutive slots,
@@ -104,6 +118,7 @@ int launch_matrix_q(const LaunchArgs &a);
 int launch_matrix_qgen(const LaunchArgs &a);
 int launch_matrix_coll(const LaunchArgs &a);
 int launch_action_vec(const LaunchArgs &a);
+int launch_action_vec_fast(const LaunchArgs &a);
 int launch_matrix_vec(const LaunchArgs &a);
 int launch_action_mixed(const LaunchArgs &a);
 int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);

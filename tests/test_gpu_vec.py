@@ -154,6 +154,79 @@ def test_full_size_48cubed_sampled(ctx, family, k):
 
 
 @pytest.fixture(scope="module")
+def ctx_box(lib):
+    c = sf.Context(0)
+    sf.sf_set_geometry(c, "box")
+    yield c
+    c.close()
+
+
+BOX_PREC = [("fp64", "f64", TOL64), ("fp64", "f32", 2e-6), ("fp32", "f64", 5e-6), ("fp32", "f32", 5e-6)]
+
+
+@pytest.mark.parametrize("family", ["NCF", "NCE"])
+@pytest.mark.parametrize("k", range(1, 7))
+@pytest.mark.parametrize("form,alpha,beta", [("MASS", 1.0, 0.0), ("DIVCURL", 0.7, 1.3)])
+@pytest.mark.parametrize("prec,io,tol", BOX_PREC)
+def test_action_box_context(ctx_box, family, k, form, alpha, beta, prec, io, tol):
+    """Box-cell contexts run the kernel with diagonal Piola factors and the pointwise
+    stage fused into the contractions: every degree, both forms, every precision and
+    storage pair, kappa per point, a cell count that leaves the last group ragged."""
+    f = FORM[family] if form == "DIVCURL" else "MASS"
+    grid = (3, 3, 5) if k <= 3 else (2, 3, 4)
+    V = synth.box_mesh(*grid, 240 + k)[:-1]
+    n = len(V)
+    npio = np.float32 if io == "f32" else np.float64
+    nd = oracle.ndof(family, k)
+    kap = synth.kappa(n, (k + 1) ** 3, 240 + k).astype(npio)
+    u = synth.dof_vector(n, nd, 240 + k).astype(npio)
+    print("case", family, k, f, prec, io, n, flush=True)
+    op = sf.make_op(family, k, f, precision=prec, io=io, alpha=alpha, beta=beta)
+    y, flags = gpu_action(ctx_box, op, V, kap, u, io=npio)
+    ref = oracle.action(family, k, f, V, u.astype(np.float64), kappa=kap.astype(np.float64), alpha=alpha, beta=beta)
+    assert flags == 0
+    assert rel_l2(y, ref) <= tol, (rel_l2(y, ref), max_cell_rel(y, ref))
+
+
+@pytest.mark.parametrize("family", ["NCF", "NCE"])
+@pytest.mark.parametrize("k", [2, 5])
+def test_box_context_flags_sheared_cells(ctx_box, family, k):
+    """A box context applies only the diagonal Piola factors: sheared cells raise
+    SF_FLAG_NONBOX, boxes do not."""
+    nd = oracle.ndof(family, k)
+    V = synth.affine_cells(5, 250 + k)
+    u = synth.dof_vector(len(V), nd, 250 + k)
+    _, flags = gpu_action(ctx_box, sf.make_op(family, k, FORM[family]), V, None, u)
+    assert flags & sf.SF_FLAG_NONBOX
+    V = synth.box_mesh(1, 2, 3, 251 + k)
+    _, flags = gpu_action(ctx_box, sf.make_op(family, k, FORM[family]), V, None, synth.dof_vector(6, nd, 3))
+    assert flags == 0
+
+
+@pytest.mark.parametrize("family", ["NCF", "NCE"])
+@pytest.mark.parametrize("k", range(1, 7))
+@pytest.mark.parametrize("io", ["f64", "f32"])
+def test_box_context_48cubed_sampled(ctx_box, family, k, io):
+    """The 48^3-cell workload in the benchmark's launch (box context, alpha = beta = 1,
+    kappa = 1, FP64 contractions, FP64 or FP32 storage): 40 evenly spaced cells (first
+    and last included) against the oracle; outputs pre-filled with NaN."""
+    V = synth.box_mesh(48, 48, 48, 4)
+    n = len(V)
+    nd = oracle.ndof(family, k)
+    npio = np.float32 if io == "f32" else np.float64
+    u = synth.dof_vector(n, nd, 4).astype(npio)
+    dy = empty((n, nd), npio)
+    dy.fill_(np.nan)
+    sf.assemble_action(ctx_box, sf.make_op(family, k, FORM[family], io=io), n, dev(V), None, dev(u), dy)
+    assert sf.sf_check_errors(ctx_box) == 0
+    y = host(dy)
+    assert np.isfinite(y).all()
+    idx = np.unique(np.concatenate([np.linspace(0, n - 1, 40).astype(np.int64), [n - 1]]))
+    ref = oracle.action(family, k, FORM[family], V[idx], u[idx].astype(np.float64))
+    assert rel_l2(y[idx], ref) <= (TOL64 if io == "f64" else 2e-6)
+
+
+@pytest.fixture(scope="module")
 def ctx_tri(lib):
     c = sf.Context(0)
     sf.sf_set_geometry(c, "trilinear")
