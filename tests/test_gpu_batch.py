@@ -177,6 +177,14 @@ def test_autotune_cache_roundtrip(ctx):
                 key = "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|%s" % (
                     op2.family, op2.degree, op2.form, op2.degree + 1, op2.precision, op2.io_dtype, what)
                 assert key in data and 0 <= data[key] < 6, key
+        # H(div) / H(curl): the stand-alone kernel choice on box cells (variants 0..2)
+        for op2 in (sf.make_op("NCF", 2, "HDIV"), sf.make_op("NCE", 3, "HCURL", io="f32")):
+            sf.sf_autotune(ctx, op2, 2000, path)
+            data = json.load(open(path))
+            key = "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|standalone" % (
+                op2.family, op2.degree, op2.form, op2.degree + 1, op2.precision, op2.io_dtype)
+            assert key in data and 0 <= data[key] <= 2, key
+        # a class with no kernel choice
         with pytest.raises(sf.SfError) as e:
-            sf.sf_autotune(ctx, sf.make_op("NCF", 2, "HDIV"), 1000, path)
+            sf.sf_autotune(ctx, sf.make_op("VQ", 2, "LAPLACE"), 1000, path)
         assert e.value.code == sf.SF_ERR_UNSUPPORTED
