@@ -283,8 +283,8 @@ def roofline_of(p, ms, ncells, variant):
     nflops = action_flops_per_cell(p) * ncells
     gbs, tfl = nbytes / t / 1e9, nflops / t / 1e12
     hbm_frac, alu_frac = gbs / PEAK_HBM_GBS, tfl / PEAK_FP64_TFLOPS
-    kernel = "%s Q_%d Laplace FP64 (variant %d)" % ("action_q_kernel" if variant == 3 else "action_q_fast_kernel",
-                                                    p, variant)
+    name = {3: "action_q_kernel", 6: "action_q_cell2_kernel"}.get(variant, "action_q_fast_kernel")
+    kernel = "%s Q_%d Laplace FP64 (variant %d)" % (name, p, variant)
     common = {"traffic": recorded_traffic(p, variant), "kernel": kernel, "time_ms": round(ms, 4),
               "bytes_per_launch": nbytes, "flops_per_launch": nflops,
               "hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4),

@@ -367,7 +367,8 @@ int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
  *     SF_GEOM_BOX (0: prefetch of the next cell group, >= 3 workgroups per
  *     CU; 1: no prefetch, >= 4; 2: prefetch, >= 2; 3: the general
  *     three-tensor kernel that SF_GEOM_AFFINE uses; 4 and 5: 128-thread
- *     workgroups with and without prefetch);
+ *     workgroups with and without prefetch; 6, p = 1 only: one cell per
+ *     thread in registers, no LDS);
  *   "standalone" (SF_NCF, SF_NCE; SF_FP64 or SF_FP32; either storage): the
  *     H(div) / H(curl) action kernel used under SF_GEOM_BOX (0: diagonal
  *     Piola factors with the pointwise stage fused into the contractions;

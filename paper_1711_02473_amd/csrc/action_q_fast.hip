@@ -98,6 +98,107 @@ __global__ void __launch_bounds__(NT, MINB)
     }
 }
 
+// p = 1 (two points per axis): one cell per thread, no LDS.  The cell's 24 vertex
+// coordinates, 8 DOFs and 8 coefficients are read as 16-byte vectors into registers
+// (each thread a contiguous run; the lines a wave touches are used in full), the
+// tensor-product stages run on [2][2][2] register arrays, and the 8 results are
+// written the same way.  Same operator as the group kernels: interpolate with B
+// (skipped for the collocated families), the diagonal box factor on the gradient
+// (Laplace) or w kappa |J| (mass), transposed contractions.
+template <int FORM, bool COLL, typename T, typename IO>
+__global__ void __launch_bounds__(256)
+    action_q_cell2_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
+                          const IO *__restrict__ u, IO *__restrict__ y, const T *__restrict__ tab,
+                          int *__restrict__ err)
+{
+    constexpr TabLayout TL(2, 0, 2);
+    const cptr<T> B = fresh(tab + TL.B0()), Dh = fresh(tab + TL.Dh()), W = fresh(tab + TL.W());
+    for (int64_t gc = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; gc < ncells;
+         gc += int64_t(gridDim.x) * blockDim.x) {
+        double X[24];
+        const double2 *xv = reinterpret_cast<const double2 *>(vert + gc * 24);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const double2 v = xv[i];
+            X[2 * i] = v.x;
+            X[2 * i + 1] = v.y;
+        }
+        T uc[8], kc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) uc[i] = T(to_d(u[gc * 8 + i]));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) kc[i] = kappa != nullptr ? T(to_d(kappa[gc * 8 + i])) : T(1);
+        double J[3][3], det;
+        int f = affine_jacobian(X, J, det);
+        double P[3];
+        if constexpr (FORM == SF_LAPLACE) {
+            double PF[6];
+            laplace_factor(J, det, PF);
+            P[0] = PF[0];
+            P[1] = PF[3];
+            P[2] = PF[5];
+            const double off = fabs(J[0][1]) + fabs(J[0][2]) + fabs(J[1][0]) + fabs(J[1][2]) + fabs(J[2][0]) +
+                               fabs(J[2][1]);
+            const double dia = fabs(J[0][0]) + fabs(J[1][1]) + fabs(J[2][2]);
+            if (off > 1e-14 * dia) f |= SF_FLAG_NONBOX; // only the diagonal of G G^T is applied
+        } else {
+            P[0] = P[1] = P[2] = fabs(det);
+        }
+        if (f) atomicOr(err, f);
+        // one-axis application of a 2 x 2 matrix M (row-major [q][i]) or its transpose
+        auto ax = [&](const cptr<T> &M, bool tr, int a, const T (&in)[8], T (&out)[8]) {
+            const int s = a == 0 ? 4 : (a == 1 ? 2 : 1);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t & s) continue;
+                const T x0 = in[t], x1 = in[t + s];
+                const T m00 = T(M[0]), m01 = tr ? T(M[2]) : T(M[1]), m10 = tr ? T(M[1]) : T(M[2]), m11 = T(M[3]);
+                out[t] = fmadd(m00, x0, m01 * x1);
+                out[t + s] = fmadd(m10, x0, m11 * x1);
+            }
+        };
+        T ut[8], t1[8];
+        if constexpr (COLL) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ut[i] = uc[i];
+        } else {
+            ax(B, false, 0, uc, ut);
+            ax(B, false, 1, ut, t1);
+            ax(B, false, 2, t1, ut);
+        }
+        T wv[8];
+        // point weights w_q0 w_q1 w_q2 kappa_q
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kc[q] *= T(W[q >> 2]) * T(W[(q >> 1) & 1]) * T(W[q & 1]);
+        if constexpr (FORM == SF_MASS) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) wv[q] = T(P[0]) * kc[q] * ut[q];
+        } else {
+            T g[8], h[8];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ax(Dh, false, a, ut, g);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) g[q] *= T(P[a]) * kc[q];
+                ax(Dh, true, a, g, h);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) wv[q] = a == 0 ? h[q] : wv[q] + h[q];
+            }
+        }
+        T yo[8];
+        if constexpr (COLL) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) yo[i] = wv[i];
+        } else {
+            ax(B, true, 2, wv, t1);
+            ax(B, true, 1, t1, wv);
+            ax(B, true, 0, wv, yo);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[gc * 8 + i] = IO(yo[i]);
+    }
+}
+
 namespace {
 
 template <typename K> int grid_for(K kernel, int nt, int64_t groups, int *cache)
@@ -132,9 +233,23 @@ int launch_fast_v(const LaunchArgs &a, const T *tab)
 // 256-thread workgroups: 0 = prefetch, >= 3 workgroups/CU; 1 = no prefetch, >= 4;
 // 2 = prefetch, >= 2.  128-thread workgroups (fewer cells per group, more groups in
 // flight): 4 = prefetch, >= 6 workgroups/CU; 5 = no prefetch, >= 8.
+template <int FORM, bool COLL, typename T, typename IO>
+int launch_cell2(const LaunchArgs &a, const T *tab)
+{
+    const int64_t blocks = std::min<int64_t>((a.ncells + 255) / 256, int64_t(1) << 20);
+    hipLaunchKernelGGL((action_q_cell2_kernel<FORM, COLL, T, IO>), dim3(unsigned(blocks)), dim3(256), 0, a.stream,
+                       a.ncells, a.vert, static_cast<const IO *>(a.kappa), static_cast<const IO *>(a.u),
+                       static_cast<IO *>(a.y), tab, a.err);
+    return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
 template <int N, int FORM, bool COLL, typename T, typename IO>
 int launch_fast(const LaunchArgs &a, const T *tab)
 {
+    if (a.variant == 6) {
+        if constexpr (N == 2) return launch_cell2<FORM, COLL, T, IO>(a, tab);
+        return SF_ERR_UNSUPPORTED;
+    }
     switch (a.variant) {
     case 1: return launch_fast_v<N, FORM, COLL, T, IO, false, 4>(a, tab);
     case 2: return launch_fast_v<N, FORM, COLL, T, IO, true, 2>(a, tab);

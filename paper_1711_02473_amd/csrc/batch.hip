@@ -604,7 +604,8 @@ int sf_autotune(sf_context *ctx, const sf_op *op, int64_t ncells_hint, const cha
         LaunchArgs a;
         ok = ensure_tables(ctx, op, a) == SF_OK;
         float best_sa_ms = 1e30f;
-        for (int v = 0; ok && v < 6; ++v) {
+        for (int v = 0; ok && v < 7; ++v) {
+            if (v == 6 && op->degree != 1) continue; // one cell per thread: p = 1 only
             a.ncells = nc;
             a.vert = vert;
             a.kappa = kap;

@@ -25,6 +25,11 @@ TOL64 = 1e-12
 VARIANTS = (0, 1, 2, 3, 4, 5)
 
 
+def variants_for(p):
+    """Every variant the autotuner may pick at degree p (6, one cell per thread, is p = 1 only)."""
+    return VARIANTS + ((6,) if p == 1 else ())
+
+
 @pytest.fixture(scope="module")
 def ctx(lib):
     c = sf.Context(0)
@@ -65,7 +70,7 @@ def test_box_action_fp64_all_variants(ctx, tmp_path, family, form, p):
     u = synth.dof_vector(n, nd, 11)
     ref = oracle.action(family, p, form, V, u, kappa=kap)
     op = sf.make_op(family, p, form)
-    for v in VARIANTS:
+    for v in variants_for(p):
         print("case", family, form, p, n, "variant", v, flush=True)
         force_variant(ctx, op, v, tmp_path)
         y, flags = launch(ctx, op, V, kap, u)
@@ -93,11 +98,28 @@ def test_box_action_fp32(ctx, tmp_path, prec, io, tol, p):
     ref = oracle.action("Q", p, "LAPLACE", V, u.astype(npio).astype(np.float64),
                         kappa=kap.astype(npio).astype(np.float64))
     op = sf.make_op("Q", p, "LAPLACE", precision=prec, io=io)
-    for v in VARIANTS:
+    for v in variants_for(p):
         force_variant(ctx, op, v, tmp_path)
         y, flags = launch(ctx, op, V, kap, u, io=npio)
         assert flags == 0
         assert rel_l2(y, ref) <= tol, (v, rel_l2(y, ref))
+
+
+def test_cell_kernel_flags_p1(ctx, tmp_path):
+    """The one-cell-per-thread kernel (p = 1) raises the same flags as the group kernels:
+    SF_FLAG_NONBOX on sheared cells, nothing on boxes, SF_FLAG_DETJ on a collapsed box."""
+    op = sf.make_op("Q", 1, "LAPLACE")
+    force_variant(ctx, op, 6, tmp_path)
+    u = synth.dof_vector(16, 8, 15)
+    _, f = launch(ctx, op, synth.affine_cells(16, 15), None, u)
+    assert f & sf.SF_FLAG_NONBOX
+    boxes = synth.box_mesh(2, 2, 4, 15)
+    _, f = launch(ctx, op, boxes, None, u)
+    assert f == 0
+    flat = boxes.copy()
+    flat[5, :, 0] = flat[5, 0, 0]
+    _, f = launch(ctx, op, flat, None, u)
+    assert f & sf.SF_FLAG_DETJ
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -159,7 +181,7 @@ def test_box_full_size_sampled(ctx, tmp_path, form, p):
     kh, uh = host(kap[ti]), host(u[ti])
     ref = oracle.action("Q", p, form, Vh[idx], uh, kappa=kh)
     op = sf.make_op("Q", p, form)
-    for v in VARIANTS:
+    for v in variants_for(p):
         print("case full-size", form, "p", p, "variant", v, flush=True)
         force_variant(ctx, op, v, tmp_path)
         y.fill_(np.nan)
