@@ -492,7 +492,7 @@ int sf_load_tuning(sf_context *ctx, const char *path)
 {
     if (!ctx || !path) return SF_ERR_ARG;
     for (auto &kv : read_json(path))
-        if (kv.second >= 0 && kv.second < 6) ctx->tuned[kv.first] = kv.second;
+        if (kv.second >= 0 && kv.second <= 6) ctx->tuned[kv.first] = kv.second; // variants 0..6
     return SF_OK;
 }
 
