@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sf_internal.hpp"
+#include "kron_layout.hpp"
 
 using namespace sf;
 
@@ -115,6 +116,61 @@ std::vector<uint16_t> mixed_planes(const std::vector<double> &h, const TabLayout
                 base[768] = fp16_bits(v);
             }
     return m;
+}
+
+// Dense Kronecker table block of the low-degree mixed-precision action (layout in
+// kron_layout.hpp) from the FP64 tables B = B0 [nq][n] and D = D0 [nq][n], n = nq <= 4.
+std::vector<uint16_t> kron_block(const std::vector<double> &h, const TabLayout &L, int n)
+{
+    const KronLayout K(n);
+    std::vector<uint16_t> out(K.total(), 0);
+    const int nd = K.nd;
+    auto B = [&](int q, int i) { return h[L.B0() + q * n + i]; };
+    auto D = [&](int q, int i) { return h[L.D0() + q * n + i]; };
+    // G_mat[q][i]; mat 0: B B B, 1: D B B, 2: B D B, 3: B B D (first factor on axis 0)
+    auto G = [&](int mat, int q, int i) {
+        if (q >= nd || i >= nd) return 0.0;
+        const int q0 = q / (n * n), q1 = (q / n) % n, q2 = q % n;
+        const int i0 = i / (n * n), i1 = (i / n) % n, i2 = i % n;
+        return (mat == 1 ? D(q0, i0) : B(q0, i0)) * (mat == 2 ? D(q1, i1) : B(q1, i1)) *
+               (mat == 3 ? D(q2, i2) : B(q2, i2));
+    };
+    auto planes = [&](double v, uint16_t p[4]) {
+        p[0] = bf16_bits(v);
+        const double r1 = v - bf16_value(p[0]);
+        p[1] = bf16_bits(r1);
+        p[2] = bf16_bits(r1 - bf16_value(p[1]));
+        p[3] = fp16_bits(v);
+    };
+    for (int mat = 0; mat < 4; ++mat) {
+        for (int m = 0; m < K.MT; ++m)
+            for (int s = 0; s < K.KS; ++s)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        uint16_t p[4];
+                        planes(G(mat, 16 * m + l % 16, 32 * s + 8 * (l / 16) + j), p);
+                        const int e = ((m * K.KS + s) * 64 + l) * 8 + j;
+                        for (int pl = 0; pl < 4; ++pl) out[K.fwd(mat, pl) + e] = p[pl];
+                    }
+        for (int t = 0; t < K.NT; ++t)
+            for (int m2 = 0; m2 < K.MT2; ++m2)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        uint16_t p[4];
+                        planes(G(mat, 32 * m2 + 16 * (j / 4) + 4 * (l / 16) + j % 4, 16 * t + l % 16), p);
+                        const int e = ((t * K.MT2 + m2) * 64 + l) * 8 + j;
+                        for (int pl = 0; pl < 4; ++pl) out[K.bwd(mat, pl) + e] = p[pl];
+                    }
+    }
+    for (int q = 0; q < K.MT * 16; ++q) {
+        float w = 0.0f;
+        if (q < nd) {
+            const int q0 = q / (n * n), q1 = (q / n) % n, q2 = q % n;
+            w = float(h[L.W() + q0] * h[L.W() + q1] * h[L.W() + q2]);
+        }
+        std::memcpy(&out[K.w3() + 2 * q], &w, 4);
+    }
+    return out;
 }
 
 // Even-odd packing of a square n x n row-major matrix M at h[src] with
@@ -263,6 +319,17 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
             (void)hipFree(ts.mixed);
             return SF_ERR_HIP;
         }
+        if (d.n0 == d.nq1 && d.nq1 <= kKronMaxN) {
+            std::vector<uint16_t> kb = kron_block(h, L, d.nq1);
+            if (hipMalloc(&ts.kron, sizeof(uint16_t) * kb.size()) != hipSuccess ||
+                hipMemcpy(ts.kron, kb.data(), sizeof(uint16_t) * kb.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipFree(ts.d64);
+                (void)hipFree(ts.f32);
+                (void)hipFree(ts.mixed);
+                (void)hipFree(ts.kron);
+                return SF_ERR_NOMEM;
+            }
+        }
     }
     auto res = ctx->tables.emplace(key, ts);
     *out = &res.first->second;
@@ -294,6 +361,7 @@ int make_args(sf_context *ctx, const sf_op *op, int64_t ncells, const double *ve
     a.tab64 = ts->d64;
     a.tab32 = ts->f32;
     a.tabmix = ts->mixed;
+    a.tabkron = ts->kron;
     a.err = ctx->d_err;
     a.stream = static_cast<hipStream_t>(stream);
     a.variant = 0;
@@ -395,6 +463,7 @@ int sf_context_destroy(sf_context *ctx)
         (void)hipFree(kv.second.d64);
         (void)hipFree(kv.second.f32);
         if (kv.second.mixed) (void)hipFree(kv.second.mixed);
+        if (kv.second.kron) (void)hipFree(kv.second.kron);
     }
     (void)hipFree(ctx->d_err);
     (void)hipFree(ctx->d_sched);
@@ -443,8 +512,12 @@ int assemble_action(sf_context *ctx, const sf_op *op, int64_t ncells, const doub
         a.trilinear = ctx->geometry == SF_GEOM_TRILINEAR;
         return launch_action_vq(a);
     }
-    if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3)
+    if (op->precision == SF_BF16 || op->precision == SF_FP16 || op->precision == SF_BF16X3) {
+        // variant 0: the dense Kronecker form where it is built (n = p + 1 <= 4), else
+        // the sum-factorised kernel; 1: always the sum-factorised kernel
+        a.variant = tuned_variant_of(ctx, op, "standalone", 0);
         return launch_action_mixed(a);
+    }
     if (scalar_family(op->family)) {
         if (ctx->geometry == SF_GEOM_TRILINEAR) {
             a.trilinear = true;

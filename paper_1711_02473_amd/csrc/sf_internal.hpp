@@ -75,6 +75,7 @@ struct TableSet {
     double *d64 = nullptr;
     float *f32 = nullptr;
     void *mixed = nullptr; // low-precision tables (layout owned by mixed.hip)
+    void *kron = nullptr;  // dense Kronecker tables for n <= 4 (layout in kron_layout.hpp)
 };
 
 struct LaunchArgs {
@@ -89,6 +90,7 @@ struct LaunchArgs {
     const double *tab64;
     const float *tab32;
     const void *tabmix;
+    const void *tabkron = nullptr;
     int *err;
     hipStream_t stream;
     int variant;
@@ -121,6 +123,7 @@ int launch_action_vec(const LaunchArgs &a);
 int launch_action_vec_fast(const LaunchArgs &a);
 int launch_matrix_vec(const LaunchArgs &a);
 int launch_action_mixed(const LaunchArgs &a);
+int launch_action_kron(const LaunchArgs &a); // mixed precision, n = p + 1 <= 4
 int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);
 
 // host-side table block of one element (TabLayout order, FP64)

@@ -3,6 +3,8 @@ against the FP64 oracle.  BF16X3 (three-term split operands) must reach
 relative L2 <= 1e-6; single-term BF16 / FP16 have no accuracy target in the
 paper and are checked against loose bounds derived from their unit roundoff
 (2^-9 and 2^-12 relative per rounding, a dozen contractions deep)."""
+import json
+
 import numpy as np
 import pytest
 
@@ -118,3 +120,67 @@ def test_mixed_element_matrix_rejections(ctx, ctx_box):
         with pytest.raises(sf.SfError) as e:
             sf.assemble_element_matrix(c, op, 2, V, None, A)
         assert e.value.code == sf.SF_ERR_UNSUPPORTED
+
+
+def force_variant(ctx, op, variant, tmp_path):
+    key = "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|standalone" % (
+        op.family, op.degree, op.form, op.degree + 1, op.precision, op.io_dtype)
+    path = tmp_path / ("tune_%d.json" % variant)
+    path.write_text(json.dumps({key: variant}))
+    sf.sf_load_tuning(ctx, str(path))
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16", "bf16"])
+@pytest.mark.parametrize("family,form", [("Q", "LAPLACE"), ("Q", "MASS"), ("DQ", "LAPLACE"), ("QGLL", "LAPLACE")])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_mixed_dense_and_sumfact_kernels(ctx, tmp_path, mode, family, form, p):
+    """p <= 3: the dense Kronecker kernel (variant 0, the default) and the
+    sum-factorised kernel (variant 1) on sheared affine cells, 117 cells (seven
+    16-cell tiles and a ragged one), both against the oracle; FP32 storage too."""
+    n = 117
+    V = synth.affine_cells(n, 230 + p)
+    nd = (p + 1) ** 3
+    kap = synth.kappa(n, nd, 230 + p)
+    u = synth.dof_vector(n, nd, 230 + p)
+    ref = oracle.action(family, p, form, V, u, kappa=kap)
+    for io, npio in (("f64", np.float64), ("f32", np.float32)):
+        op = sf.make_op(family, p, form, precision=mode, io=io)
+        ref_io = ref if io == "f64" else oracle.action(
+            family, p, form, V, u.astype(npio).astype(np.float64), kappa=kap.astype(npio).astype(np.float64))
+        got = {}
+        for v in (0, 1):
+            print("case dense/sumfact", mode, family, form, p, io, "variant", v, flush=True)
+            force_variant(ctx, op, v, tmp_path)
+            y, flags = run(ctx, op, V, kap, u, io=npio)
+            assert flags == 0
+            assert np.isfinite(y).all()
+            err = rel_l2(y, ref_io)
+            assert err <= max(BOUND[mode], 3e-7 if io == "f32" else 0.0), (v, err)
+            got[v] = y
+        force_variant(ctx, op, 0, tmp_path)  # the module's context keeps the default
+        # the two kernels round differently (operands of different contractions), both
+        # within the bound; their difference is within twice the bound
+        assert rel_l2(got[0], got[1]) <= 2 * BOUND[mode]
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_mixed_dense_full_size_sampled(ctx, mode, p):
+    """The mixed-precision benchmark configuration at p <= 3 (64^3 box cells, kappa per
+    point, FP64 storage) on the dense kernel; sampled cells against the oracle."""
+    import torch
+    n1 = 64
+    n, nd = n1 ** 3, (p + 1) ** 3
+    Vh = synth.box_mesh(n1, n1, n1, 2)
+    (kap, u), = synth.device_action_inputs(n, nd, 2, p)
+    y = torch.empty_like(u)
+    y.fill_(np.nan)
+    op = sf.make_op("Q", p, "LAPLACE", precision=mode)
+    print("case dense full-size", mode, "p", p, flush=True)
+    sf.assemble_action(ctx, op, n, dev(Vh), kap, u, y)
+    assert sf.sf_check_errors(ctx) == 0
+    assert bool(torch.isfinite(y).all())
+    idx = np.unique(np.concatenate([np.arange(0, n, 4099), np.arange(n - 9, n), [0, 1, 2, 3, n // 2]]))
+    ti = torch.from_numpy(idx).cuda()
+    ref = oracle.action("Q", p, "LAPLACE", Vh[idx], host(u[ti]), kappa=host(kap[ti]))
+    assert rel_l2(host(y[ti]), ref) <= BOUND[mode]
