@@ -173,6 +173,78 @@ std::vector<uint16_t> kron_block(const std::vector<double> &h, const TabLayout &
     return out;
 }
 
+// Split Kronecker tables of the mixed-precision action at 5 <= n <= 9 (layout in
+// kron_layout.hpp) from the FP64 tables B = B0 [nq][n] and D = D0 [nq][n], n = nq.
+std::vector<uint16_t> kron2_block(const std::vector<double> &h, const TabLayout &L, int n)
+{
+    const Kron2Layout K(n);
+    std::vector<uint16_t> out(K.total(), 0);
+    const int q2 = K.q2;
+    auto B = [&](int q, int i) { return h[L.B0() + q * n + i]; };
+    auto D = [&](int q, int i) { return h[L.D0() + q * n + i]; };
+    // plane matrix pm [q1 n + q2][i1 n + i2]: 0 B B, 1 D B, 2 B D (first factor on axis 1)
+    auto Pm = [&](int pm, int q, int i) {
+        if (q >= q2 || i >= q2) return 0.0;
+        const int q1 = q / n, qq = q % n, i1 = i / n, ii = i % n;
+        return (pm == 1 ? D(q1, i1) : B(q1, i1)) * (pm == 2 ? D(qq, ii) : B(qq, ii));
+    };
+    // block-diagonal axis-0 matrix am (0 B, 1 D) on tile rows (slot, q0) x (slot, i0)
+    auto Mb = [&](int am, int r, int c) {
+        if (r / K.rs != c / K.rs || r / K.rs >= K.cpt) return 0.0;
+        const int q = r % K.rs, i = c % K.rs;
+        if (q >= n || i >= n) return 0.0;
+        return am == 1 ? D(q, i) : B(q, i);
+    };
+    auto planes = [&](double v, uint16_t p[4]) {
+        p[0] = bf16_bits(v);
+        const double r1 = v - bf16_value(p[0]);
+        p[1] = bf16_bits(r1);
+        p[2] = bf16_bits(r1 - bf16_value(p[1]));
+        p[3] = fp16_bits(v);
+    };
+    for (int pm = 0; pm < 3; ++pm) {
+        for (int c = 0; c < K.NQ; ++c)
+            for (int k = 0; k < K.KS; ++k)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        uint16_t p[4];
+                        planes(Pm(pm, 16 * c + l % 16, 32 * k + 8 * (l / 16) + j), p);
+                        const int e = ((c * K.KS + k) * 64 + l) * 8 + j;
+                        for (int pl = 0; pl < 4; ++pl) out[K.s1f(pm, pl) + e] = p[pl];
+                    }
+        for (int t = 0; t < K.NQ; ++t)
+            for (int m = 0; m < K.NQ2; ++m)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        uint16_t p[4];
+                        planes(Pm(pm, 32 * m + 16 * (j / 4) + 4 * (l / 16) + j % 4, 16 * t + l % 16), p);
+                        const int e = ((t * K.NQ2 + m) * 64 + l) * 8 + j;
+                        for (int pl = 0; pl < 4; ++pl) out[K.s1b(pm, pl) + e] = p[pl];
+                    }
+    }
+    for (int am = 0; am < 2; ++am)
+        for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 4; ++j) {
+                uint16_t pf[4], pb[4];
+                planes(Mb(am, l % 16, 4 * (l / 16) + j), pf);
+                planes(Mb(am, 4 * (l / 16) + j, l % 16), pb);
+                for (int pl = 0; pl < 4; ++pl) {
+                    out[K.s2f(am, pl) + l * 4 + j] = pf[pl];
+                    out[K.s2b(am, pl) + l * 4 + j] = pb[pl];
+                }
+            }
+    for (int q = 0; q < K.NQ * 16; ++q) {
+        const float w = q < q2 ? float(h[L.W() + q / n] * h[L.W() + q % n]) : 0.0f;
+        std::memcpy(&out[K.w2() + 2 * q], &w, 4);
+    }
+    for (int r = 0; r < 16; ++r) {
+        const int q = r % K.rs;
+        const float w = (r / K.rs < K.cpt && q < n) ? float(h[L.W() + q]) : 0.0f;
+        std::memcpy(&out[K.w0() + 2 * r], &w, 4);
+    }
+    return out;
+}
+
 // Even-odd packing of a square n x n row-major matrix M at h[src] with
 // M[n-1-q][n-1-i] = s M[q][i] (s = -1 when skew): for each row q < n/2 the
 // entries (M[q][i] + M[q][n-1-i]) / 2 for i < n/2, M[q][n/2] when n is odd,
@@ -319,8 +391,8 @@ int build_tables(sf_context *ctx, const sf_op *op, const Dims &d, TableSet **out
             (void)hipFree(ts.mixed);
             return SF_ERR_HIP;
         }
-        if (d.n0 == d.nq1 && d.nq1 <= kKronMaxN) {
-            std::vector<uint16_t> kb = kron_block(h, L, d.nq1);
+        if (d.n0 == d.nq1 && d.nq1 <= kKron2MaxN) {
+            std::vector<uint16_t> kb = d.nq1 <= kKronMaxN ? kron_block(h, L, d.nq1) : kron2_block(h, L, d.nq1);
             if (hipMalloc(&ts.kron, sizeof(uint16_t) * kb.size()) != hipSuccess ||
                 hipMemcpy(ts.kron, kb.data(), sizeof(uint16_t) * kb.size(), hipMemcpyHostToDevice) != hipSuccess) {
                 (void)hipFree(ts.d64);

@@ -47,3 +47,53 @@ struct KronLayout {
 constexpr int kKronMaxN = 4; // the dense form is built for n <= 4 (p <= 3)
 
 } // namespace sf
+
+namespace sf {
+
+// Layout of the split Kronecker tables of the mixed-precision action at 5 <= n <= 9
+// points per axis (host-built in api.cpp, read by mixed_kron2.hip).
+//
+// A cell's interpolation factors as a dense n^2 x n^2 matrix on axes 1 and 2 (the
+// plane index i1 n + i2, resp. q1 n + q2) and an n x n matrix on axis 0:
+//   plane matrices  P0 = B (x) B,  P1 = D (x) B,  P2 = B (x) D   (first factor on axis 1)
+//   axis-0 matrices M0 = B,        M1 = D
+// (values and the three reference gradients: (P0, M1), (P1, M0), (P2, M0); the mass
+// form (P0, M0)).  The rows of an MFMA tile are (cell slot, i0): with n <= 8 two cells
+// share a tile (rows 8 s + i0), with n = 9 one cell (rows i0).  Per plane of every
+// matrix (bf16 hi, mid, lo, fp16), uint16:
+//   s1f  [NQ][KS][64 lanes][8]  B operand of v_mfma_f32_16x16x32: slot j of lane l is
+//        P[16 c + l%16][32 k + 8 (l/16) + j]   (point column c, DOF step k)
+//   s1b  [NQ][NQ2][64][8]      A operand of v_mfma_f32_16x16x32 for P^T: slot j of lane
+//        l is P[32 m + 16 (j/4) + 4 (l/16) + j%4][16 t + l%16]   (DOF row tile t,
+//        point step m: two point tiles, in the order the products deliver them)
+//   s2f  [64][4]  A operand of v_mfma_f32_16x16x16: slot j of lane l is
+//        Mblk[l%16][4 (l/16) + j]
+//   s2b  [64][4]  B operand of v_mfma_f32_16x16x16: slot j of lane l is
+//        Mblk[4 (l/16) + j][l%16]
+// with Mblk the block-diagonal 16 x 16 matrix holding M once per cell slot (zero
+// outside n x n blocks); entries outside the matrices are zero.  After the tables:
+// the plane weights w_q1 w_q2 (NQ * 16 floats) and the axis-0 weights per tile row
+// (16 floats), zero past the points.
+struct Kron2Layout {
+    int n, q2, cpt, rs, NQ, KS, NQ2;
+    constexpr Kron2Layout(int n_)
+        : n(n_), q2(n_ * n_), cpt(n_ <= 8 ? 2 : 1), rs(n_ <= 8 ? 8 : 16), NQ((n_ * n_ + 15) / 16),
+          KS((n_ * n_ + 31) / 32), NQ2(((n_ * n_ + 15) / 16 + 1) / 2)
+    {
+    }
+    constexpr int s1f_elems() const { return NQ * KS * 512; }
+    constexpr int s1b_elems() const { return NQ * NQ2 * 512; }
+    constexpr int s1_plane() const { return s1f_elems() + s1b_elems(); }
+    // uint16 offsets: plane matrix pm in 0..2, axis-0 matrix am in 0..1, plane pl in 0..3
+    constexpr int s1f(int pm, int pl) const { return (pm * 4 + pl) * s1_plane(); }
+    constexpr int s1b(int pm, int pl) const { return s1f(pm, pl) + s1f_elems(); }
+    constexpr int s2f(int am, int pl) const { return 12 * s1_plane() + (am * 4 + pl) * 512; }
+    constexpr int s2b(int am, int pl) const { return s2f(am, pl) + 256; }
+    constexpr int w2() const { return 12 * s1_plane() + 8 * 512; } // uint16 offset, 4-byte aligned
+    constexpr int w0() const { return w2() + 2 * NQ * 16; }
+    constexpr int total() const { return w0() + 2 * 16; }
+};
+
+constexpr int kKron2MinN = 5, kKron2MaxN = 9;
+
+} // namespace sf

@@ -93,7 +93,11 @@ int launch_action_mixed(const LaunchArgs &a)
 {
     if (a.family != SF_Q && a.family != SF_DQ && a.family != SF_QGLL) return SF_ERR_UNSUPPORTED;
     if (a.nq != a.degree + 1 || !a.tabmix) return SF_ERR_UNSUPPORTED;
-    if (a.variant != 1 && a.tabkron) return launch_action_kron(a);
+    if (a.variant != 1 && a.tabkron) {
+        // the dense Kronecker kernels; tables too large for LDS fall through
+        const int rc = a.degree + 1 <= 4 ? launch_action_kron(a) : launch_action_kron2(a);
+        if (rc != SF_ERR_UNSUPPORTED) return rc;
+    }
     switch (a.degree + 1) {
     case 2: return launch_n<2>(a);
     case 3: return launch_n<3>(a);

@@ -123,7 +123,8 @@ int launch_action_vec(const LaunchArgs &a);
 int launch_action_vec_fast(const LaunchArgs &a);
 int launch_matrix_vec(const LaunchArgs &a);
 int launch_action_mixed(const LaunchArgs &a);
-int launch_action_kron(const LaunchArgs &a); // mixed precision, n = p + 1 <= 4
+int launch_action_kron(const LaunchArgs &a);  // mixed precision, n = p + 1 <= 4
+int launch_action_kron2(const LaunchArgs &a); // mixed precision, 5 <= n <= 9
 int launch_dofmap_q(int nx, int ny, int nz, int p, int32_t *map, hipStream_t s);
 
 // host-side table block of one element (TabLayout order, FP64)

@@ -132,12 +132,14 @@ def force_variant(ctx, op, variant, tmp_path):
 
 @pytest.mark.parametrize("mode", ["bf16x3", "fp16", "bf16"])
 @pytest.mark.parametrize("family,form", [("Q", "LAPLACE"), ("Q", "MASS"), ("DQ", "LAPLACE"), ("QGLL", "LAPLACE")])
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", range(1, 9))
 def test_mixed_dense_and_sumfact_kernels(ctx, tmp_path, mode, family, form, p):
-    """p <= 3: the dense Kronecker kernel (variant 0, the default) and the
+    """The dense Kronecker kernels (variant 0, the default: one n^3 x n^3 product at
+    p <= 3, plane x axis-0 products at p = 4..8, BF16x3 at p = 8 excepted) and the
     sum-factorised kernel (variant 1) on sheared affine cells, 117 cells (seven
-    16-cell tiles and a ragged one), both against the oracle; FP32 storage too."""
-    n = 117
+    16-cell tiles and a ragged one; an odd count, so the last two-cell tile holds
+    one cell), both against the oracle; FP32 storage too."""
+    n = 117 if p <= 6 else 37
     V = synth.affine_cells(n, 230 + p)
     nd = (p + 1) ** 3
     kap = synth.kappa(n, nd, 230 + p)
@@ -164,10 +166,10 @@ def test_mixed_dense_and_sumfact_kernels(ctx, tmp_path, mode, family, form, p):
 
 
 @pytest.mark.parametrize("mode", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", range(1, 9))
 def test_mixed_dense_full_size_sampled(ctx, mode, p):
-    """The mixed-precision benchmark configuration at p <= 3 (64^3 box cells, kappa per
-    point, FP64 storage) on the dense kernel; sampled cells against the oracle."""
+    """The mixed-precision benchmark configuration (64^3 box cells, kappa per point,
+    FP64 storage) on the default kernel; sampled cells against the oracle."""
     import torch
     n1 = 64
     n, nd = n1 ** 3, (p + 1) ** 3
