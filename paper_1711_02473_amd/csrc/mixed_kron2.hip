@@ -6,7 +6,8 @@
 // are (cell slot, i0): two cells per tile for n <= 8, one for n = 9.  Per component
 // a (values, or the three reference gradients) and per 16 plane points:
 //   stage 1    V[i0][q']  = sum_{i'} u[i0][i'] P_a[q'][i']    (16x16x32, K = plane DOFs)
-//   stage 2    g[q0][q']  = sum_{i0} M_a[q0][i0] V[i0][q']    (16x16x16, K = axis-0 DOFs)
+//   stage 2    g[q0][q']  = sum_{i0} M_a[q0][i0] V[i0][q']    (16x16x16, K = axis-0 DOFs;
+//                                                             BF16X3: two products per 16x16x32)
 //   pointwise  s_a = w kappa sum_b P_ab g_b                   (FP32; P = |J| G G^T in FP64)
 //   stage 2^T  t[q'][i0]  = sum_{q0} s_a[q0][q'] M_a[q0][i0]  (16x16x16, K = axis-0 points)
 //   stage 1^T  y[i'][i0] += sum_{q'} P_a[q'][i'] t[q'][i0]    (16x16x32, K = plane points)
@@ -48,11 +49,17 @@ template <int N, int FORM, int MODE> struct K2Smem {
 
 // Workgroup shape: at most 128 VGPRs (single term) or 168 (three-term split), and
 // more waves per workgroup where the tables allow only one workgroup per CU
-template <int N, int FORM, int MODE> struct K2Cfg {
+#ifndef KRON2_PF
+#define KRON2_PF 1
+#endif
+template <int N, int FORM, int MODE, typename IO> struct K2Cfg {
     static constexpr bool X3 = MODE == SF_BF16X3;
+    // load the next tile's u during the current one (not where the registers run out:
+    // the three-term split, FP64 storage at n = 9)
+    static constexpr bool PF = !X3 && !(N == 9 && sizeof(IO) == 8) && KRON2_PF;
     static constexpr bool BIG = K2Smem<N, FORM, MODE>::bytes > 80 * 1024;
-    static constexpr int WAVES = BIG ? (X3 ? 12 : 16) : 8;
-    static constexpr int WPE = X3 ? 3 : 4;
+    static constexpr int WPE = X3 || PF ? 3 : 4;
+    static constexpr int WAVES = BIG ? (WPE == 3 ? 12 : 16) : 8;
 };
 
 // the axis-0 matrix of component a: D for the axis-0 gradient, B otherwise
@@ -64,7 +71,7 @@ template <int FORM> __device__ __forceinline__ constexpr int am_of(int a)
 } // namespace
 
 template <int N, int FORM, int MODE, typename IO, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(K2Cfg<N, FORM, MODE>::WPE, 8)))
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(K2Cfg<N, FORM, MODE, IO>::WPE, 8)))
     action_kron2_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                         const IO *__restrict__ u, IO *__restrict__ y, const uint16_t *__restrict__ tab,
                         int *__restrict__ err)
@@ -130,19 +137,33 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         __builtin_amdgcn_sched_barrier(0);
         const int64_t left = ncells - bt * 16;
         const int nunit = left >= 16 ? UPB : int((left + CPT - 1) / CPT);
+        // every load is unconditional: rows past the cells, DOFs and points past the cell
+        // read inside the last cell; those u values become zero, those kappa values meet
+        // a zero weight.  u as the A operand of stage 1: row col = (slot, i0), DOFs
+        // 32 ks + 8 g + j.  Single-term modes load the next tile's u while the current
+        // one computes (registers the three-term split does not have).
+        constexpr bool PF = K2Cfg<N, FORM, MODE, IO>::PF;
+        const int uslot = col / RS, ui0 = col % RS;
+        auto load_u = [&](int kk, IO (&raw)[KS][8]) {
+            const int64_t cell = bt * 16 + int64_t(CPT) * kk + uslot;
+            const IO *ur = u + (cell < ncells ? cell : ncells - 1) * N3 + (ui0 < N ? ui0 : N - 1) * Q2;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int i = 32 * ks + 8 * g + j;
+                    raw[ks][j] = ur[i < Q2 ? i : Q2 - 1];
+                }
+        };
+        IO uraw[KS][8];
+        if constexpr (PF) load_u(0, uraw);
 #pragma unroll 1
         for (int k = 0; k < nunit; ++k) {
             const int64_t c0 = bt * 16 + int64_t(CPT) * k; // first cell of the tile
-            // every load is unconditional: rows past the cells, DOFs and points past the
-            // cell read inside the last cell; those u values become zero, those kappa
-            // values meet a zero weight
-            // ---- u as the A operand of stage 1: row col = (slot, i0), DOFs 32 ks + 8 g + j
             u32x4 ua[KS][NPL];
             {
-                const int slot = col / RS, i0 = col % RS;
-                const int64_t cell = c0 + slot;
-                const bool ok = slot < CPT && i0 < N && cell < ncells;
-                const IO *ur = u + (cell < ncells ? cell : ncells - 1) * N3 + (i0 < N ? i0 : N - 1) * Q2;
+                if constexpr (!PF) load_u(k, uraw);
+                const bool ok = uslot < CPT && ui0 < N && c0 + uslot < ncells;
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -151,8 +172,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
                         for (int e = 0; e < 2; ++e) {
                             const int i = 32 * ks + 8 * g + j + e;
-                            const float v = float(to_d(ur[i < Q2 ? i : Q2 - 1]));
-                            x[e] = (ok && i < Q2) ? v : 0.0f;
+                            x[e] = (ok && i < Q2) ? float(to_d(uraw[ks][j + e])) : 0.0f;
                         }
                         uint32_t t[3];
                         terms2<MODE>(x[0], x[1], t);
@@ -167,6 +187,21 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
             for (int e = 0; e < 6; ++e) P[e] = __shfl(Pm[e], CPT * k + pslot);
             const int64_t pcell = c0 + pslot;
             const IO *kr = kappa != nullptr ? kappa + (pcell < ncells ? pcell : ncells - 1) * N3 : nullptr;
+            // kappa at rows 4 g + j, plane points 16 c + col: the whole tile's loads up
+            // front in the single-term modes, then the next tile's u
+            IO kraw[PF ? NQ : 1][4];
+            if constexpr (PF) {
+                if (kr != nullptr) {
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int q0 = (4 * g + j) % RS, qp = 16 * c + col;
+                            kraw[c][j] = kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)];
+                        }
+                }
+                if (k + 1 < nunit) load_u(k + 1, uraw);
+            }
 
             f32x4 yacc[NQ];
 #pragma unroll
@@ -214,8 +249,19 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                         for (int p = 0; p < NPL; ++p)
                             af[p] = reinterpret_cast<const u32x2 *>(s2 + (am_of<FORM>(a) * NPL + p) * 512)[lane];
                         G[a] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                        if constexpr (NPROD == 6) {
+                            // two products per K = 32 product: slots 0-3 one term pair,
+                            // slots 4-7 the next (the K order is the same on both sides)
 #pragma unroll
-                        for (int q = 0; q < NPROD; ++q) G[a] = mfma16<MODE>(af[prod_a(q)], vb[prod_b(q)], G[a]);
+                            for (int q = 0; q < 6; q += 2)
+                                G[a] = mfma32<MODE>(u32x4{af[prod_a(q)][0], af[prod_a(q)][1], af[prod_a(q + 1)][0],
+                                                          af[prod_a(q + 1)][1]},
+                                                    u32x4{vb[prod_b(q)][0], vb[prod_b(q)][1], vb[prod_b(q + 1)][0],
+                                                          vb[prod_b(q + 1)][1]},
+                                                    G[a]);
+                        } else {
+                            G[a] = mfma16<MODE>(af[0], vb[0], G[a]);
+                        }
                     }
                     // ---- pointwise on rows 4 g + j (axis-0 point (4 g + j) % RS of the
                     // lane's cell) and plane point 16 c + col
@@ -225,8 +271,11 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int q0 = (4 * g + j) % RS;
-                        const float kq =
-                            kr != nullptr ? float(to_d(kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)])) : 1.0f;
+                        float kq = 1.0f;
+                        if (kr != nullptr) {
+                            if constexpr (PF) kq = float(to_d(kraw[c][j]));
+                            else kq = float(to_d(kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)]));
+                        }
                         const float om = sW0[4 * g + j] * w2 * kq; // zero past the axis-0 points
                         if constexpr (FORM == SF_LAPLACE) {
                             const float gx = G[0][j], gy = G[1][j], gz = G[2][j];
@@ -253,8 +302,17 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                         for (int p = 0; p < NPL; ++p)
                             bm[p] = reinterpret_cast<const u32x2 *>(s2 + (am_of<FORM>(a) * NPL + p) * 512 + 256)[lane];
                         f32x4 T = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                        if constexpr (NPROD == 6) {
 #pragma unroll
-                        for (int q = 0; q < NPROD; ++q) T = mfma16<MODE>(sa[prod_b(q)], bm[prod_a(q)], T);
+                            for (int q = 0; q < 6; q += 2)
+                                T = mfma32<MODE>(u32x4{sa[prod_b(q)][0], sa[prod_b(q)][1], sa[prod_b(q + 1)][0],
+                                                       sa[prod_b(q + 1)][1]},
+                                                 u32x4{bm[prod_a(q)][0], bm[prod_a(q)][1], bm[prod_a(q + 1)][0],
+                                                       bm[prod_a(q + 1)][1]},
+                                                 T);
+                        } else {
+                            T = mfma16<MODE>(sa[0], bm[0], T);
+                        }
                         uint32_t t0[3], t1[3];
                         terms2<MODE>(T[0], T[1], t0);
                         terms2<MODE>(T[2], T[3], t1);
@@ -306,7 +364,7 @@ namespace {
 template <int N, int FORM, int MODE, typename IO>
 int launch_kron2_one(const LaunchArgs &a)
 {
-    constexpr int WAVES = K2Cfg<N, FORM, MODE>::WAVES;
+    constexpr int WAVES = K2Cfg<N, FORM, MODE, IO>::WAVES;
     static_assert(K2Smem<N, FORM, MODE>::bytes <= 160 * 1024, "LDS");
     auto kern = action_kron2_kernel<N, FORM, MODE, IO, WAVES>;
     static int cache = 0;
