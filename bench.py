@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--degrees", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
-    ap.add_argument("--mixed-degrees", default="4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
+    ap.add_argument("--mixed-degrees", default="1,2,3,4,5,6,7,8", help="degrees of the mixed-precision leg ('' = off)")
     ap.add_argument("--tune", choices=("cached", "run", "off"), default="cached",
                     help="kernel variants: 'cached' loads the autotuner's recorded choices for this GPU "
                          "(paper_1711_02473_amd/tuning/gfx950.json) and tunes what it lacks; 'run' autotunes "
@@ -690,9 +690,12 @@ def batch_leg(sf, ctx, stream, nmeshes=2048, arena_bytes=2 << 30):
 
 def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
     """Laplace action with lower-precision contractions (FP32 on the vector
-    ALUs; BF16 / FP16 single term and BF16 x3 split on MFMA), geometry and
-    pointwise factors in FP64, against the FP64 GPU path on the same inputs:
-    rate, speed-up and relative L2 difference.  Rows without a suffix keep FP64
+    ALUs; BF16 / FP16 single term and BF16 x3 split on MFMA: the dense
+    Kronecker kernels, one n^3 x n^3 product per component at p <= 3 and plane x
+    axis-0 products at p = 4..8, BF16 x3 at p = 8 on the sum-factorised MFMA
+    kernel), geometry and pointwise factors in FP64, against the FP64 GPU path on
+    the same inputs: rate, algorithmic HBM GB/s (u, y, kappa at the row's storage
+    width plus the vertices), speed-up and relative L2 difference.  Rows without a suffix keep FP64
     storage; rows "_f32io" also store kappa, u and y in FP32 (the inputs are
     rounded once, outside the timed region, and the error is measured against
     the FP64 result of the unrounded inputs, so it includes that rounding).
@@ -734,7 +737,9 @@ def mixed_leg(sf, ctx, V, bufs, ncells, degrees, ms64, glob, reps, stream):
             err = float(torch.linalg.vector_norm(ym.double() - ref) / torch.linalg.vector_norm(ref))
             t = float(np.median([a.elapsed_time(b) for a, b in ts]))
             key = mode if io == "f64" else mode + "_f32io"
+            gbs = action_bytes_per_cell(p, 8 if io == "f64" else 4) * ncells / (t / 1e3) / 1e9
             row[key] = {"ms": round(t, 4), "gdofs_global": round(glob[p] / (t / 1e3) / 1e9, 3),
+                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
                         "speedup_vs_fp64": round(ms64[p] / t, 3), "rel_l2_vs_fp64_gpu": float("%.3e" % err),
                         "_sample": ym[sample_idx(ncells)].double().cpu().numpy()}
             del sets, ym

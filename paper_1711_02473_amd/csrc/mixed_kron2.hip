@@ -58,7 +58,7 @@ template <int N, int FORM, int MODE, typename IO> struct K2Cfg {
     // the three-term split, FP64 storage at n = 9)
     static constexpr bool PF = !X3 && !(N == 9 && sizeof(IO) == 8) && KRON2_PF;
     static constexpr bool BIG = K2Smem<N, FORM, MODE>::bytes > 80 * 1024;
-    static constexpr int WPE = X3 || PF ? 3 : 4;
+    static constexpr int WPE = X3 || PF ? 3 : 4; // FP64 storage at n = 9: occupancy over the spill
     static constexpr int WAVES = BIG ? (WPE == 3 ? 12 : 16) : 8;
 };
 
