@@ -187,18 +187,21 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
             for (int e = 0; e < 6; ++e) P[e] = __shfl(Pm[e], CPT * k + pslot);
             const int64_t pcell = c0 + pslot;
             const IO *kr = kappa != nullptr ? kappa + (pcell < ncells ? pcell : ncells - 1) * N3 : nullptr;
-            // kappa at rows 4 g + j, plane points 16 c + col: the whole tile's loads up
-            // front in the single-term modes, then the next tile's u
-            IO kraw[PF ? NQ : 1][4];
+            // kappa at rows 4 g + j, plane points 16 c + col: in the single-term modes the
+            // whole tile's loads up front with FP32 storage (per pair of point tiles with
+            // FP64 storage, where the registers run out), then the next tile's u
+            constexpr bool KUP = PF && sizeof(IO) == 4;
+            auto kload = [&](int c, int j) {
+                const int q0 = (4 * g + j) % RS, qp = 16 * c + col;
+                return kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)];
+            };
+            IO kraw[KUP ? NQ : 1][4];
             if constexpr (PF) {
-                if (kr != nullptr) {
+                if (KUP && kr != nullptr) {
 #pragma unroll
                     for (int c = 0; c < NQ; ++c)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int q0 = (4 * g + j) % RS, qp = 16 * c + col;
-                            kraw[c][j] = kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)];
-                        }
+                        for (int j = 0; j < 4; ++j) kraw[c][j] = kload(c, j);
                 }
                 if (k + 1 < nunit) load_u(k + 1, uraw);
             }
@@ -211,6 +214,15 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                 // B operand of stage 1^T: the stage-2^T results of plane-point tiles
                 // 2 m (slots 0-3) and 2 m + 1 (slots 4-7)
                 u32x4 tb[NMAT][NPL];
+                IO kpair[2][4];
+                if constexpr (PF && !KUP) {
+                    if (kr != nullptr) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) kpair[h][j] = kload(2 * m + h < NQ ? 2 * m + h : NQ - 1, j);
+                    }
+                }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int c = 2 * m + h;
@@ -273,8 +285,9 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                         const int q0 = (4 * g + j) % RS;
                         float kq = 1.0f;
                         if (kr != nullptr) {
-                            if constexpr (PF) kq = float(to_d(kraw[c][j]));
-                            else kq = float(to_d(kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)]));
+                            if constexpr (KUP) kq = float(to_d(kraw[c][j]));
+                            else if constexpr (PF) kq = float(to_d(kpair[h][j]));
+                            else kq = float(to_d(kload(c, j)));
                         }
                         const float om = sW0[4 * g + j] * w2 * kq; // zero past the axis-0 points
                         if constexpr (FORM == SF_LAPLACE) {
@@ -324,6 +337,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                     }
                     if constexpr (NPL > 1) __builtin_amdgcn_sched_barrier(0);
                 }
+                __builtin_amdgcn_sched_barrier(0);
                 // ---- stage 1^T: these 32 plane points' share of every plane-DOF tile
 #pragma unroll
                 for (int t = 0; t < NQ; ++t) {
@@ -337,6 +351,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
                         for (int q = 0; q < NPROD; ++q) yacc[t] = mfma32<MODE>(af[prod_a(q)], tb[a][prod_b(q)], yacc[t]);
                     }
+                    if (t % 2 == 1) __builtin_amdgcn_sched_barrier(0); // two DOF tiles' fragments at a time
                 }
                 __builtin_amdgcn_sched_barrier(0); // one pair of point tiles' registers at a time
             }
