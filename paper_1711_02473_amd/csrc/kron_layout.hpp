@@ -58,8 +58,8 @@ namespace sf {
 //   plane matrices  P0 = B (x) B,  P1 = D (x) B,  P2 = B (x) D   (first factor on axis 1)
 //   axis-0 matrices M0 = B,        M1 = D
 // (values and the three reference gradients: (P0, M1), (P1, M0), (P2, M0); the mass
-// form (P0, M0)).  The rows of an MFMA tile are (cell slot, i0): with n <= 8 two cells
-// share a tile (rows 8 s + i0), with n = 9 one cell (rows i0).  Per plane of every
+// form (P0, M0)).  The rows of an MFMA tile are (cell slot s, i0), row rs s + i0: three
+// cells at n = 5 (rs = 5), two at n = 6..8 (rs = 8), one at n = 9 (rs = 16).  Per plane of every
 // matrix (bf16 hi, mid, lo, fp16), uint16:
 //   s1f  [NQ][KS][64 lanes][8]  B operand of v_mfma_f32_16x16x32: slot j of lane l is
 //        P[16 c + l%16][32 k + 8 (l/16) + j]   (point column c, DOF step k)
@@ -77,7 +77,8 @@ namespace sf {
 struct Kron2Layout {
     int n, q2, cpt, rs, NQ, KS, NQ2;
     constexpr Kron2Layout(int n_)
-        : n(n_), q2(n_ * n_), cpt(n_ <= 8 ? 2 : 1), rs(n_ <= 8 ? 8 : 16), NQ((n_ * n_ + 15) / 16),
+        : n(n_), q2(n_ * n_), cpt(n_ == 5 ? 3 : (n_ <= 8 ? 2 : 1)), rs(n_ == 5 ? 5 : (n_ <= 8 ? 8 : 16)),
+          NQ((n_ * n_ + 15) / 16),
           KS((n_ * n_ + 31) / 32), NQ2(((n_ * n_ + 15) / 16 + 1) / 2)
     {
     }

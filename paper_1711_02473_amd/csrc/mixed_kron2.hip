@@ -3,7 +3,7 @@
 //
 // The interpolation of a cell splits into a dense n^2 x n^2 matrix P on axes 1
 // and 2 (kron_layout.hpp) and an n x n matrix M on axis 0; the rows of an MFMA tile
-// are (cell slot, i0): two cells per tile for n <= 8, one for n = 9.  Per component
+// are (cell slot, i0): three cells per tile for n = 5, two for n = 6..8, one for n = 9.  Per component
 // a (values, or the three reference gradients) and per 16 plane points:
 //   stage 1    V[i0][q']  = sum_{i'} u[i0][i'] P_a[q'][i']    (16x16x32, K = plane DOFs)
 //   stage 2    g[q0][q']  = sum_{i0} M_a[q0][i0] V[i0][q']    (16x16x16, K = axis-0 DOFs;
@@ -124,19 +124,22 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
-    constexpr int UPB = 16 / CPT; // units (tiles of CPT cells) per batch of 16 cells
-    const int64_t nbatch = (ncells + 15) / 16;
+    // a batch is the cells of 16 / CPT tiles (16, or 15 with three cells per tile)
+    constexpr int UPB = 16 / CPT, BATCH = CPT * UPB;
+    // with RS = 5 a lane's four result rows 4 g + j may belong to two cells
+    constexpr bool ROWP = RS % 4 != 0;
+    const int64_t nbatch = (ncells + BATCH - 1) / BATCH;
     for (int64_t bt = int64_t(blockIdx.x) * WAVES + wave; bt < nbatch; bt += int64_t(gridDim.x) * WAVES) {
         // ---- FP64 geometry of the batch's 16 cells, four lanes per cell (cell 16 bt + col)
         float Pm[6];
         {
-            const int64_t c = bt * 16 + col;
-            const bool live = c < ncells;
+            const int64_t c = bt * BATCH + col;
+            const bool live = col < BATCH && c < ncells;
             cell_factor<FORM>(vert, live ? c : ncells - 1, live, col, g, err, Pm);
         }
         __builtin_amdgcn_sched_barrier(0);
-        const int64_t left = ncells - bt * 16;
-        const int nunit = left >= 16 ? UPB : int((left + CPT - 1) / CPT);
+        const int64_t left = ncells - bt * BATCH;
+        const int nunit = left >= BATCH ? UPB : int((left + CPT - 1) / CPT);
         // every load is unconditional: rows past the cells, DOFs and points past the cell
         // read inside the last cell; those u values become zero, those kappa values meet
         // a zero weight.  u as the A operand of stage 1: row col = (slot, i0), DOFs
@@ -145,7 +148,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         constexpr bool PF = K2Cfg<N, FORM, MODE, IO>::PF;
         const int uslot = col / RS, ui0 = col % RS;
         auto load_u = [&](int kk, IO (&raw)[KS][8]) {
-            const int64_t cell = bt * 16 + int64_t(CPT) * kk + uslot;
+            const int64_t cell = bt * BATCH + int64_t(CPT) * kk + uslot;
             const IO *ur = u + (cell < ncells ? cell : ncells - 1) * N3 + (ui0 < N ? ui0 : N - 1) * Q2;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         if constexpr (PF) load_u(0, uraw);
 #pragma unroll 1
         for (int k = 0; k < nunit; ++k) {
-            const int64_t c0 = bt * 16 + int64_t(CPT) * k; // first cell of the tile
+            const int64_t c0 = bt * BATCH + int64_t(CPT) * k; // first cell of the tile
             u32x4 ua[KS][NPL];
             {
                 if constexpr (!PF) load_u(k, uraw);
@@ -180,20 +183,26 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                         for (int p = 0; p < NPL; ++p) ua[ks][p][j / 2] = t[p];
                     }
             }
-            // ---- the factor of the cell of this lane's result rows 4 g + j (slot 4 g / RS)
-            const int pslot = CPT == 2 ? g / 2 : 0;
-            float P[6];
+            // ---- the factor of the cell of each of this lane's result rows 4 g + j
+            // (slot (4 g + j) / RS; one cell for all four unless RS = 5; padding rows past
+            // the tile's cells take the last slot's and meet a zero weight)
+            // (rows 4 g .. 4 g + 3 span at most two cells: the first row's and the last's)
+            float P[ROWP ? 2 : 1][6];
 #pragma unroll
-            for (int e = 0; e < 6; ++e) P[e] = __shfl(Pm[e], CPT * k + pslot);
-            const int64_t pcell = c0 + pslot;
-            const IO *kr = kappa != nullptr ? kappa + (pcell < ncells ? pcell : ncells - 1) * N3 : nullptr;
+            for (int r = 0; r < (ROWP ? 2 : 1); ++r) {
+                const int sl = (4 * g + 3 * r) / RS;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) P[r][e] = __shfl(Pm[e], CPT * k + (sl < CPT ? sl : CPT - 1));
+            }
+            const IO *kr = kappa;
             // kappa at rows 4 g + j, plane points 16 c + col: in the single-term modes the
             // whole tile's loads up front with FP32 storage (per pair of point tiles with
             // FP64 storage, where the registers run out), then the next tile's u
             constexpr bool KUP = PF && sizeof(IO) == 4;
             auto kload = [&](int c, int j) {
-                const int q0 = (4 * g + j) % RS, qp = 16 * c + col;
-                return kr[(q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)];
+                const int sl = (4 * g + j) / RS, q0 = (4 * g + j) % RS, qp = 16 * c + col;
+                const int64_t cell = c0 + sl;
+                return kr[(cell < ncells ? cell : ncells - 1) * N3 + (q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)];
             };
             IO kraw[KUP ? NQ : 1][4];
             if constexpr (PF) {
@@ -290,13 +299,17 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                             else kq = float(to_d(kload(c, j)));
                         }
                         const float om = sW0[4 * g + j] * w2 * kq; // zero past the axis-0 points
+                        float Pj[6];
+#pragma unroll
+                        for (int e = 0; e < 6; ++e)
+                            Pj[e] = ROWP && (4 * g + j) / RS != (4 * g) / RS ? P[ROWP ? 1 : 0][e] : P[0][e];
                         if constexpr (FORM == SF_LAPLACE) {
                             const float gx = G[0][j], gy = G[1][j], gz = G[2][j];
-                            sv[0][j] = om * (P[0] * gx + P[1] * gy + P[2] * gz);
-                            sv[1][j] = om * (P[1] * gx + P[3] * gy + P[4] * gz);
-                            sv[2][j] = om * (P[2] * gx + P[4] * gy + P[5] * gz);
+                            sv[0][j] = om * (Pj[0] * gx + Pj[1] * gy + Pj[2] * gz);
+                            sv[1][j] = om * (Pj[1] * gx + Pj[3] * gy + Pj[4] * gz);
+                            sv[2][j] = om * (Pj[2] * gx + Pj[4] * gy + Pj[5] * gz);
                         } else {
-                            sv[0][j] = om * P[0] * G[0][j];
+                            sv[0][j] = om * Pj[0] * G[0][j];
                         }
                     }
                     // ---- stage 2^T: s^T (A operand, the D layout of s) times M
@@ -391,7 +404,8 @@ int launch_kron2_one(const LaunchArgs &a)
             return SF_ERR_HIP;
         cache = std::max(1, per_cu) * std::max(1, ncu);
     }
-    const int64_t nbatch = (a.ncells + 15) / 16;
+    constexpr int BATCH = Kron2Layout(N).cpt * (16 / Kron2Layout(N).cpt);
+    const int64_t nbatch = (a.ncells + BATCH - 1) / BATCH;
     const int64_t blocks = std::min<int64_t>(cache, (nbatch + WAVES - 1) / WAVES);
     hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * WAVES), 0, a.stream, a.ncells, a.vert,
                        static_cast<const IO *>(a.kappa), static_cast<const IO *>(a.u), static_cast<IO *>(a.y),
