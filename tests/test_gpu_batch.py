@@ -74,6 +74,19 @@ def standalone(ctx, r, ctx_box=None):
         ctx = ctx_box  # lower-precision element matrices: the box-cell kernel
     if r["kind"] == "act":
         y = empty((r["n"], r["nd"]), np.float64)
+        if r["prec"] != "fp64":
+            # the batch's lower-precision action tiles run the sum-factorised MFMA body:
+            # compare with that stand-alone kernel (variant 1), then restore the default
+            with tempfile.TemporaryDirectory() as d:
+                key = "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|standalone" % (
+                    op.family, op.degree, op.form, op.degree + 1, op.precision, op.io_dtype)
+                for v in (1, 0):
+                    path = os.path.join(d, "v%d.json" % v)
+                    json.dump({key: v}, open(path, "w"))
+                    sf.sf_load_tuning(ctx, path)
+                    if v == 1:
+                        sf.assemble_action(ctx, op, r["n"], r["dV"], r["dk"], r["du"], y)
+            return host(y)
         sf.assemble_action(ctx, op, r["n"], r["dV"], r["dk"], r["du"], y)
         return host(y)
     A = empty((r["n"], r["nd"], r["nd"]), np.float64)

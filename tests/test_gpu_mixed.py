@@ -186,3 +186,33 @@ def test_mixed_dense_full_size_sampled(ctx, mode, p):
     ti = torch.from_numpy(idx).cuda()
     ref = oracle.action("Q", p, "LAPLACE", Vh[idx], host(u[ti]), kappa=host(kap[ti]))
     assert rel_l2(host(y[ti]), ref) <= BOUND[mode]
+
+
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("p", [1, 2, 4, 5, 7, 8])
+def test_mixed_dense_flags_and_small_counts(ctx, mode, p):
+    """Geometry flags from the dense kernels' FP64 cell factor (one non-affine cell,
+    one inverted cell, each alone in a batch of good cells), and tiny cell counts
+    (1, 2, 5: tiles and batches mostly empty) with kappa = NULL against the oracle."""
+    nd = (p + 1) ** 3
+    op = sf.make_op("Q", p, "LAPLACE", precision=mode)
+    for ncell in (1, 2, 5):
+        V = synth.affine_cells(ncell, 240 + ncell)
+        u = synth.dof_vector(ncell, nd, 240 + ncell)
+        print("case small count", mode, p, ncell, flush=True)
+        y, flags = run(ctx, op, V, None, u)
+        assert flags == 0
+        assert rel_l2(y, oracle.action("Q", p, "LAPLACE", V, u)) <= BOUND[mode]
+    V = synth.affine_cells(40, 250)
+    V_bad = V.copy()
+    V_bad[17] = synth.trilinear_cells(1, 251)[0]  # not an affine image of its first four vertices
+    u = synth.dof_vector(40, nd, 250)
+    print("case flags", mode, p, flush=True)
+    _, flags = run(ctx, op, V_bad, None, u)
+    assert flags & sf.SF_FLAG_NONAFFINE
+    V_inv = V.copy()
+    V_inv[33] = V_inv[33][[4, 5, 6, 7, 0, 1, 2, 3]]  # mirrored along axis 0: det J < 0
+    _, flags = run(ctx, op, V_inv, None, u)
+    assert flags & sf.SF_FLAG_DETJ
+    _, flags = run(ctx, op, V, None, u)
+    assert flags == 0
