@@ -115,7 +115,12 @@ enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3, SF_SVK = 4, SF_SV
  * with FP32 accumulation; BF16X3 = operands split into three BF16 terms
  * (hi + mid + lo), six cross products per contraction, FP32 accumulation.
  * Geometry, Jacobian, inverse, determinant and the pointwise factors are FP64
- * in every mode. */
+ * in every mode (the pointwise product itself is FP32).  Scalar-family
+ * actions in the MFMA modes (nq1 = degree + 1) group the contractions as
+ * dense Kronecker products (Sec. 3.3's sums, grouped differently): one
+ * (p+1)^3 x (p+1)^3 matrix per component at p <= 3, a (p+1)^2 x (p+1)^2 matrix
+ * on axes 1-2 times a (p+1) x (p+1) matrix on axis 0 at p = 4..8; BF16X3 at
+ * p = 8 and other nq1 use the one-axis-at-a-time MFMA kernel. */
 enum { SF_FP64 = 0, SF_FP32 = 1, SF_BF16 = 2, SF_FP16 = 3, SF_BF16X3 = 4 };
 /* storage type of kappa, u, y and A */
 enum { SF_F64 = 0, SF_F32 = 1 };
@@ -374,6 +379,10 @@ int sf_batch_info(const sf_batch *batch, int64_t *ntiles, int32_t *nworkgroups);
  *     Piola factors with the pointwise stage fused into the contractions;
  *     1: one cell group per workgroup; 2: the persistent kernel with full
  *     per-cell Piola factors that SF_GEOM_AFFINE uses).
+ * A "standalone" entry for a scalar-family action in SF_BF16, SF_FP16 or
+ * SF_BF16X3 selects its kernel (0, the default: the dense Kronecker
+ * kernels; 1: the one-axis-at-a-time MFMA kernel).  sf_autotune does not
+ * time that choice; sf_load_tuning accepts it.
  * When cache_json_path is non-NULL the choices are merged into that JSON
  * file, keyed by architecture, family, degree, form, nq1, precision, io dtype
  * and the choice name.  Later calls with the same key use the winners.
