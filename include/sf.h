@@ -115,7 +115,9 @@ enum { SF_MASS = 0, SF_LAPLACE = 1, SF_HDIV = 2, SF_HCURL = 3, SF_SVK = 4, SF_SV
  * with FP32 accumulation; BF16X3 = operands split into three BF16 terms
  * (hi + mid + lo), six cross products per contraction, FP32 accumulation.
  * Geometry, Jacobian, inverse, determinant and the pointwise factors are FP64
- * in every mode (the pointwise product itself is FP32).  Scalar-family
+ * in every mode (the pointwise product itself is FP32).  FP16 operands carry
+ * FP16's range: u, the interpolated values and the pointwise products must
+ * stay below 65504 in magnitude (BF16 and BF16X3 have FP32's range).  Scalar-family
  * actions in the MFMA modes (nq1 = degree + 1) group the contractions as
  * dense Kronecker products (Sec. 3.3's sums, grouped differently): one
  * (p+1)^3 x (p+1)^3 matrix per component at p <= 3, a (p+1)^2 x (p+1)^2 matrix

@@ -43,10 +43,10 @@ template <int N, int FORM, int MODE> struct KronSmem {
     static constexpr int bytes = off_w + K.MT * 16 * 4;
 };
 
-// Waves per workgroup and the register budget: single-term modes 8 waves and at most
-// 128 VGPRs (four waves per SIMD, two workgroups per CU); the three-term split needs
-// more registers (168: three waves per SIMD) and runs 12 waves per workgroup, one
-// workgroup per CU (its tables take 144 KiB of LDS at n = 4)
+// Waves per workgroup and the register budget: 8 waves and at most 128 VGPRs (four
+// waves per SIMD, two or more workgroups per CU), except the three-term split at
+// n = 4, whose tables take 144 KiB of LDS (one workgroup per CU): 12 waves of at most
+// 168 VGPRs (three per SIMD)
 template <int N, int MODE> struct KronCfg {
     static constexpr bool BIG = MODE == SF_BF16X3 && N == 4;
     static constexpr int WAVES = BIG ? 12 : 8;
