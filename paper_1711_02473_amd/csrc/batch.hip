@@ -38,6 +38,8 @@ int ensure_tables(sf_context *ctx, const sf_op *op, LaunchArgs &a);
 #include "action_q_body.inc"
 #include "matrix_q_body.inc"
 #include "mixed_body.inc"
+#include "mixed_kron2_body.inc"
+#include "mixed_kron_body.inc"
 
 namespace sf {
 
@@ -62,6 +64,7 @@ struct BatchJob {
     int64_t arena;
     const double *tab64;
     const uint16_t *mix;
+    const uint16_t *kron; // dense Kronecker tables (kron_layout.hpp)
 };
 
 struct BatchTile {
@@ -69,6 +72,11 @@ struct BatchTile {
     int pad;
     int64_t first, count;
 };
+
+// BF16x3 action tiles run the dense Kronecker bodies (tables read from global memory, no
+// LDS), except at n = 9; the single-term tiles keep the sum-factorised MFMA body, which is
+// faster here (the dense bodies reach their rates with the tables in LDS and more waves)
+template <int N, int KIND> constexpr bool kron_tiles() { return KIND == K_ACT_BF16X3 && N != 9; }
 
 template <int N> struct Cls {
     static constexpr int CA = (256 / (N * N)) > 0 ? 256 / (N * N) : 1; // FP64 action cells per group
@@ -81,6 +89,7 @@ template <int N> struct Cls {
     }
     static constexpr int smem(int kind)
     {
+        if (kind == K_ACT_BF16X3 && N != 9) return 0; // the dense Kronecker bodies use no LDS
         return kind == K_ACT_BOX   ? BoxSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
                : kind == K_ACT_F64 ? ActionQSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
                                    : (is_mat(kind) ? MatrixQSmem<N, N, SF_LAPLACE, CMAT>::bytes
@@ -101,6 +110,37 @@ __device__ __noinline__ void run_tile(const BatchJob *__restrict__ jobs, int job
 {
     const BatchJob j = jobs[job];
     const int64_t end = first + count < j.ncells ? first + count : j.ncells;
+    if constexpr (kron_tiles<N, KIND>()) {
+        // the tile's cells in 16-cell tiles (n <= 4) or geometry batches (n >= 5), one per
+        // wave in turn, every product chained in registers
+        using namespace kron;
+        constexpr int MODE = KIND == K_ACT_BF16 ? SF_BF16 : (KIND == K_ACT_FP16 ? SF_FP16 : SF_BF16X3);
+        constexpr int NW = kNT / 64;
+        const int wave = threadIdx.x >> 6;
+        if constexpr (N <= 4) {
+            constexpr KronLayout K(N);
+            constexpr int NPL = KronMode<MODE>::NPL;
+            auto plane = [](int p) { return NPL == 1 ? KronMode<MODE>::PLANE0 : p; };
+            const uint16_t *kt = j.kron;
+            auto ffrag = [&](int a, int p, int i) {
+                return reinterpret_cast<const u32x4 *>(kt + K.fwd(1 + a, plane(p)))[i];
+            };
+            auto bfrag = [&](int a, int p, int i) {
+                return reinterpret_cast<const u32x4 *>(kt + K.bwd(1 + a, plane(p)))[i];
+            };
+            const float *w3 = reinterpret_cast<const float *>(kt + K.w3());
+            for (int64_t c0 = first + 16 * wave; c0 < end; c0 += 16 * NW)
+                kron_tile<N, SF_LAPLACE, MODE, double>(c0, end, ffrag, bfrag, w3, j.vert, j.kappa, j.u, j.y, err);
+        } else {
+            constexpr Kron2Layout K(N);
+            constexpr int BATCH = K.cpt * (16 / K.cpt);
+            const Kron2GlobalTables<N, MODE> tabs{j.kron};
+            for (int64_t b0 = first + BATCH * wave; b0 < end; b0 += BATCH * NW)
+                kron2_batch<N, SF_LAPLACE, MODE, double, MODE != SF_BF16X3 && N <= 8>(b0, end, tabs, j.vert, j.kappa,
+                                                                                        j.u, j.y, err);
+        }
+        return;
+    }
     constexpr int CPG = Cls<N>::cells_per_group(KIND);
     for (int64_t g = first; g < end; g += CPG) {
         if constexpr (KIND == K_ACT_BOX) {
@@ -324,6 +364,8 @@ static int batch_build(sf_context *ctx, const sf_job *jobs, int32_t njobs, const
         b.arena = j.A_arena_cells > 0 ? j.A_arena_cells : 0;
         b.tab64 = a.tab64;
         b.mix = static_cast<const uint16_t *>(a.tabmix);
+        b.kron = static_cast<const uint16_t *>(a.tabkron);
+        if (!mat && kind != K_ACT_F64 && kind != K_ACT_BOX && !b.kron) return SF_ERR_UNSUPPORTED;
         hj.push_back(b);
         if (j.ncells == 0) continue;
         smem = std::max(smem, cls_smem(kind, n));

@@ -26,6 +26,7 @@
 
 #include "kron_common.hpp"
 #include "kron_layout.hpp"
+#include "mixed_kron_body.inc"
 
 namespace sf {
 
@@ -96,149 +97,16 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
     for (int t = threadIdx.x; t < MT * 16; t += 64 * WAVES) sW[t] = reinterpret_cast<const float *>(kron + K.w3())[t];
     __syncthreads();
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int wave = threadIdx.x >> 6;
+    auto ffrag = [&](int a, int p, int i) {
+        return reinterpret_cast<const u32x4 *>(sF + (a * NPL + p) * K.fwd_elems())[i];
+    };
+    auto bfrag = [&](int a, int p, int i) {
+        return reinterpret_cast<const u32x4 *>(sB + (a * NPL + p) * K.bwd_elems())[i];
+    };
     const int64_t ntiles = (ncells + 15) / 16;
     for (int64_t tile = int64_t(blockIdx.x) * WAVES + wave; tile < ntiles; tile += int64_t(gridDim.x) * WAVES) {
-        {
-            const int64_t cell = tile * 16 + col;
-            const bool live = cell < ncells;
-            // every load of the tile is unconditional, so all are in flight at once:
-            // columns past the last cell read the last cell, DOFs and points past nd the
-            // last one; those u values are replaced by zero, those kappa values meet a
-            // zero weight
-            const int64_t cl = live ? cell : ncells - 1;
-            // ---- FP64 geometry of the tile's cells (four lanes per cell)
-            float P[6];
-            cell_factor<FORM>(vert, cl, live, col, g, err, P);
-            __builtin_amdgcn_sched_barrier(0);
-            // ---- this lane's u fragments: DOFs 32 s + 8 g + j of cell `col`, split into terms
-            u32x4 ub[KS][NPL];
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-#pragma unroll
-                for (int j = 0; j < 8; j += 2) {
-                    float x[2];
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int i = 32 * s + 8 * g + j + e;
-                        const float v = float(to_d(u[cl * ND + (i < ND ? i : ND - 1)]));
-                        x[e] = (live && i < ND) ? v : 0.0f;
-                    }
-                    uint32_t t[3];
-                    terms2<MODE>(x[0], x[1], t);
-#pragma unroll
-                    for (int p = 0; p < NPL; ++p) ub[s][p][j / 2] = t[p];
-                }
-
-            f32x4 yacc[NTL];
-#pragma unroll
-            for (int t = 0; t < NTL; ++t) yacc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int m2 = 0; m2 < MT2; ++m2) {
-                // the results of the forward m-tiles 2 m2 and 2 m2 + 1 form, slot for slot,
-                // the B operand of one K = 32 backward product (slots 0-3 and 4-7)
-                u32x4 sb[NMAT][NPL];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int m = 2 * m2 + h;
-                    if (m >= MT) {
-#pragma unroll
-                        for (int a = 0; a < NMAT; ++a)
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p)
-#pragma unroll
-                                for (int j = 0; j < 2; ++j) sb[a][p][2 * h + j] = 0u;
-                        continue;
-                    }
-                    // ---- forward: this m-tile's points for every matrix of the form
-                    f32x4 gacc[NMAT];
-#pragma unroll
-                    for (int a = 0; a < NMAT; ++a) {
-                        gacc[a] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                        for (int s = 0; s < KS; ++s) {
-                            u32x4 af[NPL];
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p)
-                                af[p] = reinterpret_cast<const u32x4 *>(
-                                    sF + (a * NPL + p) * K.fwd_elems())[(m * KS + s) * 64 + lane];
-#pragma unroll
-                            for (int q = 0; q < NPROD; ++q)
-                                gacc[a] = mfma32<MODE>(af[prod_a(q)], ub[s][prod_b(q)], gacc[a]);
-                        }
-                    }
-                    // ---- pointwise on this lane's four points q = 16 m + 4 g + j of cell `col`
-                    float kq[4];
-                    if (kappa == nullptr) {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) kq[j] = 1.0f;
-                    } else if constexpr (ND == 16 * MT) {
-                        // every point of the tile exists (n = 4): four consecutive points of
-                        // the cell, one vector load
-                        const IO *kp = kappa + cl * ND + 16 * m + 4 * g;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) kq[j] = float(to_d(kp[j]));
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int q = 16 * m + 4 * g + j;
-                            kq[j] = float(to_d(kappa[cl * ND + (q < ND ? q : ND - 1)]));
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < 4; j += 2) {
-                        float sv[2][NMAT];
-#pragma unroll
-                        for (int e = 0; e < 2; ++e) {
-                            const int q = 16 * m + 4 * g + j + e;
-                            const float om = sW[q] * kq[j + e]; // zero past the last point
-                            if constexpr (FORM == SF_LAPLACE) {
-                                const float gx = gacc[0][j + e], gy = gacc[1][j + e], gz = gacc[2][j + e];
-                                sv[e][0] = om * (P[0] * gx + P[1] * gy + P[2] * gz);
-                                sv[e][1] = om * (P[1] * gx + P[3] * gy + P[4] * gz);
-                                sv[e][2] = om * (P[2] * gx + P[4] * gy + P[5] * gz);
-                            } else {
-                                sv[e][0] = om * P[0] * gacc[0][j + e];
-                            }
-                        }
-#pragma unroll
-                        for (int a = 0; a < NMAT; ++a) {
-                            uint32_t t[3];
-                            terms2<MODE>(sv[0][a], sv[1][a], t);
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p) sb[a][p][2 * h + j / 2] = t[p];
-                        }
-                    }
-                    if constexpr (NPL > 1) __builtin_amdgcn_sched_barrier(0);
-                }
-                // ---- backward: these 32 points' share of every DOF tile
-#pragma unroll
-                for (int t = 0; t < NTL; ++t) {
-#pragma unroll
-                    for (int a = 0; a < NMAT; ++a) {
-                        u32x4 bf[NPL];
-#pragma unroll
-                        for (int p = 0; p < NPL; ++p)
-                            bf[p] = reinterpret_cast<const u32x4 *>(
-                                sB + (a * NPL + p) * K.bwd_elems())[(t * MT2 + m2) * 64 + lane];
-#pragma unroll
-                        for (int q = 0; q < NPROD; ++q)
-                            yacc[t] = mfma32<MODE>(bf[prod_a(q)], sb[a][prod_b(q)], yacc[t]);
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0); // one pair's registers at a time
-            }
-            // ---- y: this lane's four consecutive DOFs 16 t + 4 g + j of cell `col`
-            if (live) {
-#pragma unroll
-                for (int t = 0; t < NTL; ++t)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int i = 16 * t + 4 * g + j;
-                        if (i < ND) y[cell * ND + i] = IO(yacc[t][j]);
-                    }
-            }
-        }
+        kron_tile<N, FORM, MODE, IO>(tile * 16, ncells, ffrag, bfrag, sW, vert, kappa, u, y, err);
     }
 }
 

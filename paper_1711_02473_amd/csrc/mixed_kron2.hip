@@ -26,6 +26,7 @@
 
 #include "kron_common.hpp"
 #include "kron_layout.hpp"
+#include "mixed_kron2_body.inc"
 
 namespace sf {
 
@@ -61,12 +62,6 @@ template <int N, int FORM, int MODE, typename IO> struct K2Cfg {
     static constexpr int WPE = X3 || PF ? 3 : 4; // FP64 storage at n = 9: occupancy over the spill
     static constexpr int WAVES = BIG ? (WPE == 3 ? 12 : 16) : 8;
 };
-
-// the axis-0 matrix of component a: D for the axis-0 gradient, B otherwise
-template <int FORM> __device__ __forceinline__ constexpr int am_of(int a)
-{
-    return FORM == SF_LAPLACE && a == 0 ? 1 : 0;
-}
 
 } // namespace
 
@@ -123,267 +118,35 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
     }
     __syncthreads();
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int wave = threadIdx.x >> 6;
     // a batch is the cells of 16 / CPT tiles (16, or 15 with three cells per tile)
-    constexpr int UPB = 16 / CPT, BATCH = CPT * UPB;
-    // with RS = 5 a lane's four result rows 4 g + j may belong to two cells
-    constexpr bool ROWP = RS % 4 != 0;
+    constexpr int BATCH = CPT * (16 / CPT);
+    // the LDS copy of the tables: components in order, the mode's terms only
+    struct {
+        const uint16_t *s1f_, *s1b_, *s2_;
+        const float *w2_, *w0_;
+        __device__ __forceinline__ u32x4 s1f(int a, int p, int i) const
+        {
+            return reinterpret_cast<const u32x4 *>(s1f_ + (a * NPL + p) * Kron2Layout(N).s1f_elems())[i];
+        }
+        __device__ __forceinline__ u32x4 s1b(int a, int p, int i) const
+        {
+            return reinterpret_cast<const u32x4 *>(s1b_ + (a * NPL + p) * Kron2Layout(N).s1b_elems())[i];
+        }
+        __device__ __forceinline__ u32x2 s2f(int am, int p, int lane) const
+        {
+            return reinterpret_cast<const u32x2 *>(s2_ + (am * NPL + p) * 512)[lane];
+        }
+        __device__ __forceinline__ u32x2 s2b(int am, int p, int lane) const
+        {
+            return reinterpret_cast<const u32x2 *>(s2_ + (am * NPL + p) * 512 + 256)[lane];
+        }
+        __device__ __forceinline__ float w2(int q) const { return w2_[q]; }
+        __device__ __forceinline__ float w0(int r) const { return w0_[r]; }
+    } const tabs{s1f, s1b, s2, sW2, sW0};
     const int64_t nbatch = (ncells + BATCH - 1) / BATCH;
     for (int64_t bt = int64_t(blockIdx.x) * WAVES + wave; bt < nbatch; bt += int64_t(gridDim.x) * WAVES) {
-        // ---- FP64 geometry of the batch's 16 cells, four lanes per cell (cell 16 bt + col)
-        float Pm[6];
-        {
-            const int64_t c = bt * BATCH + col;
-            const bool live = col < BATCH && c < ncells;
-            cell_factor<FORM>(vert, live ? c : ncells - 1, live, col, g, err, Pm);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        const int64_t left = ncells - bt * BATCH;
-        const int nunit = left >= BATCH ? UPB : int((left + CPT - 1) / CPT);
-        // every load is unconditional: rows past the cells, DOFs and points past the cell
-        // read inside the last cell; those u values become zero, those kappa values meet
-        // a zero weight.  u as the A operand of stage 1: row col = (slot, i0), DOFs
-        // 32 ks + 8 g + j.  Single-term modes load the next tile's u while the current
-        // one computes (registers the three-term split does not have).
-        constexpr bool PF = K2Cfg<N, FORM, MODE, IO>::PF;
-        const int uslot = col / RS, ui0 = col % RS;
-        auto load_u = [&](int kk, IO (&raw)[KS][8]) {
-            const int64_t cell = bt * BATCH + int64_t(CPT) * kk + uslot;
-            const IO *ur = u + (cell < ncells ? cell : ncells - 1) * N3 + (ui0 < N ? ui0 : N - 1) * Q2;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int i = 32 * ks + 8 * g + j;
-                    raw[ks][j] = ur[i < Q2 ? i : Q2 - 1];
-                }
-        };
-        IO uraw[KS][8];
-        if constexpr (PF) load_u(0, uraw);
-#pragma unroll 1
-        for (int k = 0; k < nunit; ++k) {
-            const int64_t c0 = bt * BATCH + int64_t(CPT) * k; // first cell of the tile
-            u32x4 ua[KS][NPL];
-            {
-                if constexpr (!PF) load_u(k, uraw);
-                const bool ok = uslot < CPT && ui0 < N && c0 + uslot < ncells;
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                    for (int j = 0; j < 8; j += 2) {
-                        float x[2];
-#pragma unroll
-                        for (int e = 0; e < 2; ++e) {
-                            const int i = 32 * ks + 8 * g + j + e;
-                            x[e] = (ok && i < Q2) ? float(to_d(uraw[ks][j + e])) : 0.0f;
-                        }
-                        uint32_t t[3];
-                        terms2<MODE>(x[0], x[1], t);
-#pragma unroll
-                        for (int p = 0; p < NPL; ++p) ua[ks][p][j / 2] = t[p];
-                    }
-            }
-            // ---- the factor of the cell of each of this lane's result rows 4 g + j
-            // (slot (4 g + j) / RS; one cell for all four unless RS = 5; padding rows past
-            // the tile's cells take the last slot's and meet a zero weight)
-            // (rows 4 g .. 4 g + 3 span at most two cells: the first row's and the last's)
-            float P[ROWP ? 2 : 1][6];
-#pragma unroll
-            for (int r = 0; r < (ROWP ? 2 : 1); ++r) {
-                const int sl = (4 * g + 3 * r) / RS;
-#pragma unroll
-                for (int e = 0; e < 6; ++e) P[r][e] = __shfl(Pm[e], CPT * k + (sl < CPT ? sl : CPT - 1));
-            }
-            const IO *kr = kappa;
-            // kappa at rows 4 g + j, plane points 16 c + col: in the single-term modes the
-            // whole tile's loads up front with FP32 storage (per pair of point tiles with
-            // FP64 storage, where the registers run out), then the next tile's u
-            constexpr bool KUP = PF && sizeof(IO) == 4;
-            auto kload = [&](int c, int j) {
-                const int sl = (4 * g + j) / RS, q0 = (4 * g + j) % RS, qp = 16 * c + col;
-                const int64_t cell = c0 + sl;
-                return kr[(cell < ncells ? cell : ncells - 1) * N3 + (q0 < N ? q0 : N - 1) * Q2 + (qp < Q2 ? qp : Q2 - 1)];
-            };
-            IO kraw[KUP ? NQ : 1][4];
-            if constexpr (PF) {
-                if (KUP && kr != nullptr) {
-#pragma unroll
-                    for (int c = 0; c < NQ; ++c)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) kraw[c][j] = kload(c, j);
-                }
-                if (k + 1 < nunit) load_u(k + 1, uraw);
-            }
-
-            f32x4 yacc[NQ];
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) yacc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int m = 0; m < NQ2; ++m) {
-                // B operand of stage 1^T: the stage-2^T results of plane-point tiles
-                // 2 m (slots 0-3) and 2 m + 1 (slots 4-7)
-                u32x4 tb[NMAT][NPL];
-                IO kpair[2][4];
-                if constexpr (PF && !KUP) {
-                    if (kr != nullptr) {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h)
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) kpair[h][j] = kload(2 * m + h < NQ ? 2 * m + h : NQ - 1, j);
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int c = 2 * m + h;
-                    if (c >= NQ) {
-#pragma unroll
-                        for (int a = 0; a < NMAT; ++a)
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p) tb[a][p][2 * h] = tb[a][p][2 * h + 1] = 0u;
-                        continue;
-                    }
-                    // ---- stage 1 and stage 2: this tile's 16 plane points, every component
-                    f32x4 G[NMAT];
-#pragma unroll
-                    for (int a = 0; a < NMAT; ++a) {
-                        f32x4 V = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                        for (int ks = 0; ks < KS; ++ks) {
-                            u32x4 bf[NPL];
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p)
-                                bf[p] = reinterpret_cast<const u32x4 *>(
-                                    s1f + (a * NPL + p) * K.s1f_elems())[(c * KS + ks) * 64 + lane];
-#pragma unroll
-                            for (int q = 0; q < NPROD; ++q) V = mfma32<MODE>(ua[ks][prod_b(q)], bf[prod_a(q)], V);
-                        }
-                        u32x2 vb[NPL];
-                        {
-                            uint32_t t0[3], t1[3];
-                            terms2<MODE>(V[0], V[1], t0);
-                            terms2<MODE>(V[2], V[3], t1);
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p) vb[p] = u32x2{t0[p], t1[p]};
-                        }
-                        u32x2 af[NPL];
-#pragma unroll
-                        for (int p = 0; p < NPL; ++p)
-                            af[p] = reinterpret_cast<const u32x2 *>(s2 + (am_of<FORM>(a) * NPL + p) * 512)[lane];
-                        G[a] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                        if constexpr (NPROD == 6) {
-                            // two products per K = 32 product: slots 0-3 one term pair,
-                            // slots 4-7 the next (the K order is the same on both sides)
-#pragma unroll
-                            for (int q = 0; q < 6; q += 2)
-                                G[a] = mfma32<MODE>(u32x4{af[prod_a(q)][0], af[prod_a(q)][1], af[prod_a(q + 1)][0],
-                                                          af[prod_a(q + 1)][1]},
-                                                    u32x4{vb[prod_b(q)][0], vb[prod_b(q)][1], vb[prod_b(q + 1)][0],
-                                                          vb[prod_b(q + 1)][1]},
-                                                    G[a]);
-                        } else {
-                            G[a] = mfma16<MODE>(af[0], vb[0], G[a]);
-                        }
-                    }
-                    // ---- pointwise on rows 4 g + j (axis-0 point (4 g + j) % RS of the
-                    // lane's cell) and plane point 16 c + col
-                    const int qp = 16 * c + col;
-                    const float w2 = sW2[qp]; // zero past the plane points
-                    float sv[NMAT][4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int q0 = (4 * g + j) % RS;
-                        float kq = 1.0f;
-                        if (kr != nullptr) {
-                            if constexpr (KUP) kq = float(to_d(kraw[c][j]));
-                            else if constexpr (PF) kq = float(to_d(kpair[h][j]));
-                            else kq = float(to_d(kload(c, j)));
-                        }
-                        const float om = sW0[4 * g + j] * w2 * kq; // zero past the axis-0 points
-                        float Pj[6];
-#pragma unroll
-                        for (int e = 0; e < 6; ++e)
-                            Pj[e] = ROWP && (4 * g + j) / RS != (4 * g) / RS ? P[ROWP ? 1 : 0][e] : P[0][e];
-                        if constexpr (FORM == SF_LAPLACE) {
-                            const float gx = G[0][j], gy = G[1][j], gz = G[2][j];
-                            sv[0][j] = om * (Pj[0] * gx + Pj[1] * gy + Pj[2] * gz);
-                            sv[1][j] = om * (Pj[1] * gx + Pj[3] * gy + Pj[4] * gz);
-                            sv[2][j] = om * (Pj[2] * gx + Pj[4] * gy + Pj[5] * gz);
-                        } else {
-                            sv[0][j] = om * Pj[0] * G[0][j];
-                        }
-                    }
-                    // ---- stage 2^T: s^T (A operand, the D layout of s) times M
-#pragma unroll
-                    for (int a = 0; a < NMAT; ++a) {
-                        u32x2 sa[NPL];
-                        {
-                            uint32_t t0[3], t1[3];
-                            terms2<MODE>(sv[a][0], sv[a][1], t0);
-                            terms2<MODE>(sv[a][2], sv[a][3], t1);
-#pragma unroll
-                            for (int p = 0; p < NPL; ++p) sa[p] = u32x2{t0[p], t1[p]};
-                        }
-                        u32x2 bm[NPL];
-#pragma unroll
-                        for (int p = 0; p < NPL; ++p)
-                            bm[p] = reinterpret_cast<const u32x2 *>(s2 + (am_of<FORM>(a) * NPL + p) * 512 + 256)[lane];
-                        f32x4 T = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                        if constexpr (NPROD == 6) {
-#pragma unroll
-                            for (int q = 0; q < 6; q += 2)
-                                T = mfma32<MODE>(u32x4{sa[prod_b(q)][0], sa[prod_b(q)][1], sa[prod_b(q + 1)][0],
-                                                       sa[prod_b(q + 1)][1]},
-                                                 u32x4{bm[prod_a(q)][0], bm[prod_a(q)][1], bm[prod_a(q + 1)][0],
-                                                       bm[prod_a(q + 1)][1]},
-                                                 T);
-                        } else {
-                            T = mfma16<MODE>(sa[0], bm[0], T);
-                        }
-                        uint32_t t0[3], t1[3];
-                        terms2<MODE>(T[0], T[1], t0);
-                        terms2<MODE>(T[2], T[3], t1);
-#pragma unroll
-                        for (int p = 0; p < NPL; ++p) {
-                            tb[a][p][2 * h] = t0[p];
-                            tb[a][p][2 * h + 1] = t1[p];
-                        }
-                    }
-                    if constexpr (NPL > 1) __builtin_amdgcn_sched_barrier(0);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                // ---- stage 1^T: these 32 plane points' share of every plane-DOF tile
-#pragma unroll
-                for (int t = 0; t < NQ; ++t) {
-#pragma unroll
-                    for (int a = 0; a < NMAT; ++a) {
-                        u32x4 af[NPL];
-#pragma unroll
-                        for (int p = 0; p < NPL; ++p)
-                            af[p] = reinterpret_cast<const u32x4 *>(
-                                s1b + (a * NPL + p) * K.s1b_elems())[(t * NQ2 + m) * 64 + lane];
-#pragma unroll
-                        for (int q = 0; q < NPROD; ++q) yacc[t] = mfma32<MODE>(af[prod_a(q)], tb[a][prod_b(q)], yacc[t]);
-                    }
-                    if (t % 2 == 1) __builtin_amdgcn_sched_barrier(0); // two DOF tiles' fragments at a time
-                }
-                __builtin_amdgcn_sched_barrier(0); // one pair of point tiles' registers at a time
-            }
-            // ---- y: column col = (slot, i0), plane DOFs 16 t + 4 g + j (four consecutive)
-            {
-                const int slot = col / RS, i0 = col % RS;
-                const int64_t cell = c0 + slot;
-                if (slot < CPT && i0 < N && cell < ncells) {
-                    IO *yr = y + cell * N3 + i0 * Q2;
-#pragma unroll
-                    for (int t = 0; t < NQ; ++t)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int i = 16 * t + 4 * g + j;
-                            if (i < Q2) yr[i] = IO(yacc[t][j]);
-                        }
-                }
-            }
-        }
+        kron2_batch<N, FORM, MODE, IO, K2Cfg<N, FORM, MODE, IO>::PF>(bt * BATCH, ncells, tabs, vert, kappa, u, y, err);
     }
 }
 

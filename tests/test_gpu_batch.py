@@ -74,9 +74,11 @@ def standalone(ctx, r, ctx_box=None):
         ctx = ctx_box  # lower-precision element matrices: the box-cell kernel
     if r["kind"] == "act":
         y = empty((r["n"], r["nd"]), np.float64)
-        if r["prec"] != "fp64":
-            # the batch's lower-precision action tiles run the sum-factorised MFMA body:
-            # compare with that stand-alone kernel (variant 1), then restore the default
+        # the batch's BF16x3 action tiles run the same dense Kronecker bodies as the
+        # stand-alone kernel (at p = 8 the sum-factorised body in both); its single-term
+        # tiles the sum-factorised body: compare with that stand-alone kernel (variant 1),
+        # then restore the default
+        if r["prec"] in ("bf16", "fp16"):
             with tempfile.TemporaryDirectory() as d:
                 key = "gfx950|fam%d|p%d|form%d|nq%d|prec%d|io%d|standalone" % (
                     op.family, op.degree, op.form, op.degree + 1, op.precision, op.io_dtype)
