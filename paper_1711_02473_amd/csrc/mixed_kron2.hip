@@ -48,19 +48,25 @@ template <int N, int FORM, int MODE> struct K2Smem {
     static constexpr int bytes = off_w0 + 4 * 16;
 };
 
-// Workgroup shape: at most 128 VGPRs (single term) or 168 (three-term split), and
-// more waves per workgroup where the tables allow only one workgroup per CU
+// Workgroup shape and register budget.  Single-term modes load the next tile's u
+// while the current one computes, at n = 9 (and n = 5 with FP32 storage) the next
+// tile's kappa as well; the three-term split has no registers for either.  Budgets:
+// 128 VGPRs (four waves per SIMD) without prefetch, 168 (three) with u alone or the
+// three-term split, 256 (two) at n = 9, where the prefetched u and kappa cover the
+// load latency that sixteen waves without them did not (FP64 storage: 1.83 -> 1.34 ms
+// on 64^3 cells).  Twelve waves per workgroup where three per SIMD fit and one
+// workgroup holds the CU, and for the three-term split everywhere; the single-term
+// modes (HBM-bound) were faster with eight.
 #ifndef KRON2_PF
 #define KRON2_PF 1
 #endif
 template <int N, int FORM, int MODE, typename IO> struct K2Cfg {
     static constexpr bool X3 = MODE == SF_BF16X3;
-    // load the next tile's u during the current one (not where the registers run out:
-    // the three-term split, FP64 storage at n = 9)
-    static constexpr bool PF = !X3 && !(N == 9 && sizeof(IO) == 8) && KRON2_PF;
+    static constexpr bool KPF = !X3 && KRON2_PF && (N == 9 || (N == 5 && sizeof(IO) == 4));
+    static constexpr bool PF = !X3 && KRON2_PF;
     static constexpr bool BIG = K2Smem<N, FORM, MODE>::bytes > 80 * 1024;
-    static constexpr int WPE = X3 || PF ? 3 : 4; // FP64 storage at n = 9: occupancy over the spill
-    static constexpr int WAVES = BIG ? (WPE == 3 ? 12 : 16) : 8;
+    static constexpr int WPE = N == 9 && PF ? 2 : (X3 || PF ? 3 : 4);
+    static constexpr int WAVES = WPE == 2 ? 8 : BIG ? (WPE == 3 ? 12 : 16) : (X3 ? 12 : 8);
 };
 
 } // namespace
@@ -146,7 +152,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
     } const tabs{s1f, s1b, s2, sW2, sW0};
     const int64_t nbatch = (ncells + BATCH - 1) / BATCH;
     for (int64_t bt = int64_t(blockIdx.x) * WAVES + wave; bt < nbatch; bt += int64_t(gridDim.x) * WAVES) {
-        kron2_batch<N, FORM, MODE, IO, K2Cfg<N, FORM, MODE, IO>::PF>(bt * BATCH, ncells, tabs, vert, kappa, u, y, err);
+        kron2_batch<N, FORM, MODE, IO, K2Cfg<N, FORM, MODE, IO>::PF, decltype(tabs), K2Cfg<N, FORM, MODE, IO>::KPF>(bt * BATCH, ncells, tabs, vert, kappa, u, y, err);
     }
 }
 
