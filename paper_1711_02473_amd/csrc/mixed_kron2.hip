@@ -53,7 +53,7 @@ template <int N, int FORM, int MODE> struct K2Smem {
 // tile's kappa as well; the three-term split has no registers for either.  Budgets:
 // 128 VGPRs (four waves per SIMD) without prefetch, 168 (three) with u alone or the
 // three-term split, 256 (two) at n = 9, where the prefetched u and kappa cover the
-// load latency that sixteen waves without them did not (FP64 storage: 1.83 -> 1.34 ms
+// load latency that sixteen waves without them did not (FP64 storage: 1.83 -> 1.25 ms
 // on 64^3 cells).  Twelve waves per workgroup where three per SIMD fit and one
 // workgroup holds the CU, and for the three-term split everywhere; the single-term
 // modes (HBM-bound) were faster with eight.
