@@ -189,20 +189,28 @@ def test_mixed_dense_full_size_sampled(ctx, mode, p):
 
 
 @pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("p", [1, 2, 4, 5, 7, 8])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_mixed_dense_flags_and_small_counts(ctx, mode, p):
     """Geometry flags from the dense kernels' FP64 cell factor (one non-affine cell,
     one inverted cell, each alone in a batch of good cells), and tiny cell counts
-    (1, 2, 5: tiles and batches mostly empty) with kappa = NULL against the oracle."""
+    (1, 2, 5: tiles and batches mostly empty, so the next-tile prefetches of u and
+    kappa stop early) with and without kappa, FP64 and FP32 storage, against the
+    oracle (on the FP32-rounded inputs for FP32 storage)."""
     nd = (p + 1) ** 3
     op = sf.make_op("Q", p, "LAPLACE", precision=mode)
     for ncell in (1, 2, 5):
         V = synth.affine_cells(ncell, 240 + ncell)
         u = synth.dof_vector(ncell, nd, 240 + ncell)
-        print("case small count", mode, p, ncell, flush=True)
-        y, flags = run(ctx, op, V, None, u)
-        assert flags == 0
-        assert rel_l2(y, oracle.action("Q", p, "LAPLACE", V, u)) <= BOUND[mode]
+        kap = synth.kappa(ncell, nd, 245 + ncell)
+        for io, npio in (("f64", np.float64), ("f32", np.float32)):
+            op_io = sf.make_op("Q", p, "LAPLACE", precision=mode, io=io)
+            for k in (None, kap):
+                print("case small count", mode, p, ncell, io, "kappa" if k is not None else "no kappa", flush=True)
+                y, flags = run(ctx, op_io, V, k, u, io=npio)
+                assert flags == 0
+                r = lambda a: None if a is None else a.astype(npio).astype(np.float64)
+                ref = oracle.action("Q", p, "LAPLACE", V, r(u), kappa=r(k))
+                assert rel_l2(y, ref) <= max(BOUND[mode], 3e-7 if io == "f32" else 0.0)
     V = synth.affine_cells(40, 250)
     V_bad = V.copy()
     V_bad[17] = synth.trilinear_cells(1, 251)[0]  # not an affine image of its first four vertices
