@@ -48,24 +48,27 @@ template <int N, int FORM, int MODE> struct K2Smem {
     static constexpr int bytes = off_w0 + 4 * 16;
 };
 
-// Workgroup shape and register budget.  Single-term modes load the next tile's u
-// while the current one computes, at n = 9 (and n = 5 with FP32 storage) the next
-// tile's kappa as well; the three-term split has no registers for either.  Budgets:
-// 128 VGPRs (four waves per SIMD) without prefetch, 168 (three) with u alone or the
-// three-term split, 256 (two) at n = 9, where the prefetched u and kappa cover the
-// load latency that sixteen waves without them did not (FP64 storage: 1.83 -> 1.25 ms
-// on 64^3 cells).  Twelve waves per workgroup where three per SIMD fit and one
-// workgroup holds the CU, and for the three-term split everywhere; the single-term
-// modes (HBM-bound) were faster with eight.
+// Workgroup shape and register budget.  The next tile's u is loaded while the current
+// one computes, and at n = 9 (single term), at n = 5 with FP32 storage (single term)
+// and in the three-term split (except n = 5 with FP32 storage) the next tile's kappa as
+// well.  Budgets: 168 VGPRs (three waves per SIMD) for the single-term modes at
+// n = 5..8 and the three-term split at n = 5 with FP32 storage, 256 (two) for the rest,
+// where the prefetched u and kappa cover the load latency that more waves without them
+// did not (64^3 cells, FP64 storage: n = 9 single term 1.83 -> 1.25 ms; three-term
+// split at n = 5..8 9-22 % faster than at three waves per SIMD without prefetch).
+// Twelve waves per workgroup where three per SIMD fit and one workgroup holds the CU,
+// and for the three-term split at n = 5 with FP32 storage; the single-term modes
+// (HBM-bound) were faster with eight.
 #ifndef KRON2_PF
 #define KRON2_PF 1
 #endif
 template <int N, int FORM, int MODE, typename IO> struct K2Cfg {
     static constexpr bool X3 = MODE == SF_BF16X3;
-    static constexpr bool KPF = !X3 && KRON2_PF && (N == 9 || (N == 5 && sizeof(IO) == 4));
-    static constexpr bool PF = !X3 && KRON2_PF;
+    static constexpr bool XPF = X3 && KRON2_PF && (sizeof(IO) == 8 || N >= 6); // three-term prefetch
+    static constexpr bool KPF = (!X3 && KRON2_PF && (N == 9 || (N == 5 && sizeof(IO) == 4))) || XPF;
+    static constexpr bool PF = (!X3 && KRON2_PF) || XPF;
     static constexpr bool BIG = K2Smem<N, FORM, MODE>::bytes > 80 * 1024;
-    static constexpr int WPE = N == 9 && PF ? 2 : (X3 || PF ? 3 : 4);
+    static constexpr int WPE = (N == 9 && PF) || XPF ? 2 : (X3 || PF ? 3 : 4);
     static constexpr int WAVES = WPE == 2 ? 8 : BIG ? (WPE == 3 ? 12 : 16) : (X3 ? 12 : 8);
 };
 
