@@ -71,20 +71,25 @@ template <int MODE> __device__ __forceinline__ f32x4 mfma16(u32x2 a, u32x2 b, f3
 
 // FP64 factor of cell `cl` (Sec. 3.2: |J| G G^T for the Laplacian, |J| for the mass
 // form), computed by each of the four lanes col + 16 g of the cell's column: lane group
-// g loads vertices 2 g and 2 g + 1, the vertices that span the Jacobian (0, 1, 2, 4) and
-// the coordinate scale are exchanged by cross-lane permutes, and each lane checks its own
-// vertices against the affine map.  Same arithmetic and flags as affine_jacobian.
-template <int FORM>
-__device__ __forceinline__ void cell_factor(const double *__restrict__ vert, int64_t cl, bool live, int col, int g,
-                                            int *__restrict__ err, float P[6])
+// g loads vertices 2 g and 2 g + 1 (cell_vertices), the vertices that span the Jacobian
+// (0, 1, 2, 4) and the coordinate scale are exchanged by cross-lane permutes, and each
+// lane checks its own vertices against the affine map (cell_factor_from).  Same
+// arithmetic and flags as affine_jacobian.
+__device__ __forceinline__ void cell_vertices(const double *__restrict__ vert, int64_t cl, int g, double (&xa)[3],
+                                              double (&xb)[3])
 {
     const double *X = vert + cl * 24 + 6 * g;
-    double xa[3], xb[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         xa[a] = X[a];
         xb[a] = X[3 + a];
     }
+}
+
+template <int FORM>
+__device__ __forceinline__ void cell_factor_from(const double (&xa)[3], const double (&xb)[3], bool live, int col,
+                                                 int g, int *__restrict__ err, float P[6])
+{
     double sc = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) sc = fmax(sc, fmax(fabs(xa[a]), fabs(xb[a])));
@@ -127,6 +132,15 @@ __device__ __forceinline__ void cell_factor(const double *__restrict__ vert, int
 #pragma unroll
         for (int e = 1; e < 6; ++e) P[e] = 0.0f;
     }
+}
+
+template <int FORM>
+__device__ __forceinline__ void cell_factor(const double *__restrict__ vert, int64_t cl, bool live, int col, int g,
+                                            int *__restrict__ err, float P[6])
+{
+    double xa[3], xb[3];
+    cell_vertices(vert, cl, g, xa, xb);
+    cell_factor_from<FORM>(xa, xb, live, col, g, err, P);
 }
 
 } // namespace kron

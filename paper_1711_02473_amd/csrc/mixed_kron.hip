@@ -46,18 +46,25 @@ template <int N, int FORM, int MODE> struct KronSmem {
 
 // Waves per workgroup and the register budget: 8 waves and at most 128 VGPRs (four
 // waves per SIMD, two or more workgroups per CU), except the three-term split at
-// n = 4, whose tables take 144 KiB of LDS (one workgroup per CU): 12 waves of at most
-// 168 VGPRs (three per SIMD)
-template <int N, int MODE> struct KronCfg {
+// n = 4, whose tables take 144 KiB of LDS (one workgroup per CU): with FP64 storage
+// 8 waves of at most 256 VGPRs (two per SIMD) that load the next tile's vertices, u
+// and kappa while the current one computes (4 % faster than without; at n <= 3 and
+// with FP32 storage the prefetch measured no faster or slower), with FP32 storage
+// 12 waves of at most 168 VGPRs (three per SIMD)
+#ifndef KRON_PF
+#define KRON_PF 1
+#endif
+template <int N, int MODE, typename IO> struct KronCfg {
     static constexpr bool BIG = MODE == SF_BF16X3 && N == 4;
-    static constexpr int WAVES = BIG ? 12 : 8;
-    static constexpr int WPE = BIG ? 3 : 4;
+    static constexpr bool PF = KRON_PF && BIG && sizeof(IO) == 8;
+    static constexpr int WAVES = PF ? 8 : BIG ? 12 : 8;
+    static constexpr int WPE = PF ? 2 : BIG ? 3 : 4;
 };
 
 } // namespace
 
 template <int N, int FORM, int MODE, typename IO, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(KronCfg<N, MODE>::WPE, 8)))
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(KronCfg<N, MODE, IO>::WPE, 8)))
     action_kron_kernel(const int64_t ncells, const double *__restrict__ vert, const IO *__restrict__ kappa,
                        const IO *__restrict__ u, IO *__restrict__ y, const uint16_t *__restrict__ kron,
                        int *__restrict__ err)
@@ -105,8 +112,12 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         return reinterpret_cast<const u32x4 *>(sB + (a * NPL + p) * K.bwd_elems())[i];
     };
     const int64_t ntiles = (ncells + 15) / 16;
-    for (int64_t tile = int64_t(blockIdx.x) * WAVES + wave; tile < ntiles; tile += int64_t(gridDim.x) * WAVES) {
-        kron_tile<N, FORM, MODE, IO>(tile * 16, ncells, ffrag, bfrag, sW, vert, kappa, u, y, err);
+    if constexpr (KronCfg<N, MODE, IO>::PF) {
+        kron_tiles_prefetch<N, FORM, MODE, IO>(int64_t(blockIdx.x) * WAVES + wave, int64_t(gridDim.x) * WAVES, ntiles,
+                                               ncells, ffrag, bfrag, sW, vert, kappa, u, y, err);
+    } else {
+        for (int64_t tile = int64_t(blockIdx.x) * WAVES + wave; tile < ntiles; tile += int64_t(gridDim.x) * WAVES)
+            kron_tile<N, FORM, MODE, IO>(tile * 16, ncells, ffrag, bfrag, sW, vert, kappa, u, y, err);
     }
 }
 
@@ -115,7 +126,7 @@ namespace {
 template <int N, int FORM, int MODE, typename IO>
 int launch_kron_one(const LaunchArgs &a)
 {
-    constexpr int WAVES = KronCfg<N, MODE>::WAVES;
+    constexpr int WAVES = KronCfg<N, MODE, IO>::WAVES;
     static_assert(KronSmem<N, FORM, MODE>::bytes <= 160 * 1024, "LDS");
     auto kern = action_kron_kernel<N, FORM, MODE, IO, WAVES>;
     static int cache = 0;
