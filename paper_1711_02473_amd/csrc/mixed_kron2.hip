@@ -48,10 +48,10 @@ template <int N, int FORM, int MODE> struct K2Smem {
     static constexpr int bytes = off_w0 + 4 * 16;
 };
 
-// Workgroup shape and register budget.  The next tile's u is loaded while the current
-// one computes, and at n = 9 (single term), at n = 5 with FP32 storage (single term)
-// and in the three-term split (except n = 5 with FP32 storage) the next tile's kappa as
-// well.  Budgets: 168 VGPRs (three waves per SIMD) for the single-term modes at
+// Workgroup shape and register budget.  Except in the three-term split at n = 5 with
+// FP32 storage, the next tile's u is loaded while the current one computes, and at
+// n = 9 (single term), at n = 5 with FP32 storage (single term) and in the other
+// three-term cases the next tile's kappa as well.  Budgets: 168 VGPRs (three waves per SIMD) for the single-term modes at
 // n = 5..8 and the three-term split at n = 5 with FP32 storage, 256 (two) for the rest,
 // where the prefetched u and kappa cover the load latency that more waves without them
 // did not (64^3 cells, FP64 storage: n = 9 single term 1.83 -> 1.25 ms; three-term
