@@ -73,10 +73,12 @@ struct BatchTile {
     int64_t first, count;
 };
 
-// BF16x3 action tiles run the dense Kronecker bodies (tables read from global memory, no
-// LDS), except at n = 9; the single-term tiles keep the sum-factorised MFMA body, which is
-// faster here (the dense bodies reach their rates with the tables in LDS and more waves)
-template <int N, int KIND> constexpr bool kron_tiles() { return KIND == K_ACT_BF16X3 && N != 9; }
+// Mixed-precision action tiles run the dense Kronecker bodies except at n = 9 (BF16x3 and
+// single term) where the sum-factorised MFMA body runs: BF16x3 with the tables read from
+// global memory (no LDS: its tables would not fit beside the other classes), the single-term
+// modes with the tables staged in LDS once per tile (at most 51.5 KB, n = 7, 8)
+template <int N, int KIND> constexpr bool kron_lds() { return (KIND == K_ACT_BF16 || KIND == K_ACT_FP16) && N <= 8; }
+template <int N, int KIND> constexpr bool kron_tiles() { return (KIND == K_ACT_BF16X3 && N != 9) || kron_lds<N, KIND>(); }
 
 template <int N> struct Cls {
     static constexpr int CA = (256 / (N * N)) > 0 ? 256 / (N * N) : 1; // FP64 action cells per group
@@ -89,7 +91,9 @@ template <int N> struct Cls {
     }
     static constexpr int smem(int kind)
     {
-        if (kind == K_ACT_BF16X3 && N != 9) return 0; // the dense Kronecker bodies use no LDS
+        if (kind == K_ACT_BF16X3 && N != 9) return 0; // the dense Kronecker bodies, global tables
+        if ((kind == K_ACT_BF16 || kind == K_ACT_FP16) && N <= 8) // the tables (BF16 and FP16 planes alike)
+            return N <= 4 ? kron::KronSmem<N, SF_LAPLACE, SF_BF16>::bytes : kron::K2Smem<N, SF_LAPLACE, SF_BF16>::bytes;
         return kind == K_ACT_BOX   ? BoxSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
                : kind == K_ACT_F64 ? ActionQSmem<N, N, SF_LAPLACE, false, double, CA>::bytes
                                    : (is_mat(kind) ? MatrixQSmem<N, N, SF_LAPLACE, CMAT>::bytes
@@ -117,27 +121,51 @@ __device__ __noinline__ void run_tile(const BatchJob *__restrict__ jobs, int job
         constexpr int MODE = KIND == K_ACT_BF16 ? SF_BF16 : (KIND == K_ACT_FP16 ? SF_FP16 : SF_BF16X3);
         constexpr int NW = kNT / 64;
         const int wave = threadIdx.x >> 6;
+        unsigned char *const sm = reinterpret_cast<unsigned char *>(batch_smem);
+        if constexpr (kron_lds<N, KIND>()) {
+            // this tile's tables into LDS (the persistent loop's barrier before the next
+            // tile keeps them until every wave is done)
+            if constexpr (N <= 4) kron_stage<N, SF_LAPLACE, MODE, kNT>(j.kron, sm);
+            else kron2_stage<N, SF_LAPLACE, MODE, kNT>(j.kron, sm);
+            __syncthreads();
+        }
         if constexpr (N <= 4) {
             constexpr KronLayout K(N);
             constexpr int NPL = KronMode<MODE>::NPL;
             auto plane = [](int p) { return NPL == 1 ? KronMode<MODE>::PLANE0 : p; };
             const uint16_t *kt = j.kron;
+            using SM = KronSmem<N, SF_LAPLACE, MODE>;
+            const uint16_t *const sF = reinterpret_cast<const uint16_t *>(sm);
+            const uint16_t *const sB = reinterpret_cast<const uint16_t *>(sm + SM::off_bwd);
             auto ffrag = [&](int a, int p, int i) {
-                return reinterpret_cast<const u32x4 *>(kt + K.fwd(1 + a, plane(p)))[i];
+                if constexpr (kron_lds<N, KIND>())
+                    return reinterpret_cast<const u32x4 *>(sF + (a * NPL + p) * K.fwd_elems())[i];
+                else
+                    return reinterpret_cast<const u32x4 *>(kt + K.fwd(1 + a, plane(p)))[i];
             };
             auto bfrag = [&](int a, int p, int i) {
-                return reinterpret_cast<const u32x4 *>(kt + K.bwd(1 + a, plane(p)))[i];
+                if constexpr (kron_lds<N, KIND>())
+                    return reinterpret_cast<const u32x4 *>(sB + (a * NPL + p) * K.bwd_elems())[i];
+                else
+                    return reinterpret_cast<const u32x4 *>(kt + K.bwd(1 + a, plane(p)))[i];
             };
-            const float *w3 = reinterpret_cast<const float *>(kt + K.w3());
+            const float *w3 = kron_lds<N, KIND>() ? reinterpret_cast<const float *>(sm + SM::off_w)
+                                                  : reinterpret_cast<const float *>(kt + K.w3());
             for (int64_t c0 = first + 16 * wave; c0 < end; c0 += 16 * NW)
                 kron_tile<N, SF_LAPLACE, MODE, double>(c0, end, ffrag, bfrag, w3, j.vert, j.kappa, j.u, j.y, err);
         } else {
             constexpr Kron2Layout K(N);
             constexpr int BATCH = K.cpt * (16 / K.cpt);
-            const Kron2GlobalTables<N, MODE> tabs{j.kron};
-            for (int64_t b0 = first + BATCH * wave; b0 < end; b0 += BATCH * NW)
-                kron2_batch<N, SF_LAPLACE, MODE, double, MODE != SF_BF16X3 && N <= 8>(b0, end, tabs, j.vert, j.kappa,
-                                                                                        j.u, j.y, err);
+            constexpr bool PF = MODE != SF_BF16X3 && N <= 8;
+            if constexpr (kron_lds<N, KIND>()) {
+                const auto tabs = Kron2LdsTables<N, SF_LAPLACE, MODE>::at(sm);
+                for (int64_t b0 = first + BATCH * wave; b0 < end; b0 += BATCH * NW)
+                    kron2_batch<N, SF_LAPLACE, MODE, double, PF>(b0, end, tabs, j.vert, j.kappa, j.u, j.y, err);
+            } else {
+                const Kron2GlobalTables<N, MODE> tabs{j.kron};
+                for (int64_t b0 = first + BATCH * wave; b0 < end; b0 += BATCH * NW)
+                    kron2_batch<N, SF_LAPLACE, MODE, double, PF>(b0, end, tabs, j.vert, j.kappa, j.u, j.y, err);
+            }
         }
         return;
     }

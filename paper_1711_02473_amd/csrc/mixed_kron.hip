@@ -34,16 +34,6 @@ using namespace kron;
 
 namespace {
 
-// LDS of one workgroup: the fragments of the matrices the form uses and the 3-D weights
-template <int N, int FORM, int MODE> struct KronSmem {
-    static constexpr KronLayout K = KronLayout(N);
-    static constexpr int NMAT = FORM == SF_LAPLACE ? 3 : 1;
-    static constexpr int NPL = KronMode<MODE>::NPL;
-    static constexpr int fwd_u16 = NMAT * NPL * K.fwd_elems(), bwd_u16 = NMAT * NPL * K.bwd_elems();
-    static constexpr int off_bwd = fwd_u16 * 2, off_w = off_bwd + bwd_u16 * 2;
-    static constexpr int bytes = off_w + K.MT * 16 * 4;
-};
-
 // Waves per workgroup and the register budget: 8 waves and at most 128 VGPRs (four
 // waves per SIMD, two or more workgroups per CU), except the three-term split at
 // n = 4, whose tables take 144 KiB of LDS (one workgroup per CU): with FP64 storage
@@ -71,37 +61,14 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 {
     using SM = KronSmem<N, FORM, MODE>;
     constexpr KronLayout K = SM::K;
-    constexpr int ND = K.nd, MT = K.MT, MT2 = K.MT2, KS = K.KS, NTL = K.NT;
-    constexpr int NMAT = SM::NMAT, NPL = SM::NPL, NPROD = KronMode<MODE>::NPROD;
-    constexpr int MAT0 = FORM == SF_LAPLACE ? 1 : 0; // first table matrix the form uses
+    constexpr int NPL = SM::NPL;
     __shared__ __align__(16) unsigned char smem[SM::bytes];
     uint16_t *const sF = reinterpret_cast<uint16_t *>(smem);
     uint16_t *const sB = reinterpret_cast<uint16_t *>(smem + SM::off_bwd);
     float *const sW = reinterpret_cast<float *>(smem + SM::off_w);
 
-    // ---- the fragments of the used matrices and planes, once per workgroup: every
-    // thread issues all of its 16-byte loads before the first LDS store
-    {
-        constexpr int FW = K.fwd_elems() / 8, BW = K.bwd_elems() / 8; // 16-byte words per block
-        constexpr int NBLK = NMAT * NPL, TOT = NBLK * (FW + BW), R = (TOT + 64 * WAVES - 1) / (64 * WAVES);
-        uint4 v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            int t = int(threadIdx.x) + r * 64 * WAVES;
-            t = t < TOT ? t : TOT - 1;
-            const bool fw = t < NBLK * FW;
-            const int tt = fw ? t : t - NBLK * FW;
-            const int mp = fw ? tt / FW : tt / BW, e = fw ? tt % FW : tt % BW;
-            const int mat = MAT0 + mp / NPL, pl = NPL == 1 ? KronMode<MODE>::PLANE0 : mp % NPL;
-            v[r] = reinterpret_cast<const uint4 *>(kron + (fw ? K.fwd(mat, pl) : K.bwd(mat, pl)))[e];
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int t = int(threadIdx.x) + r * 64 * WAVES;
-            if (t < TOT) reinterpret_cast<uint4 *>(smem)[t] = v[r]; // sF then sB, contiguous
-        }
-    }
-    for (int t = threadIdx.x; t < MT * 16; t += 64 * WAVES) sW[t] = reinterpret_cast<const float *>(kron + K.w3())[t];
+    // ---- the fragments of the used matrices and planes, once per workgroup
+    kron_stage<N, FORM, MODE, 64 * WAVES>(kron, smem);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6;

@@ -34,20 +34,6 @@ using namespace kron;
 
 namespace {
 
-// LDS of one workgroup: the plane-matrix fragments (forward, then transposed) of the
-// components the form uses, the axis-0 fragments, the plane and axis-0 weights
-template <int N, int FORM, int MODE> struct K2Smem {
-    static constexpr Kron2Layout K = Kron2Layout(N);
-    static constexpr int NMAT = FORM == SF_LAPLACE ? 3 : 1; // plane matrices (one per component)
-    static constexpr int NAM = FORM == SF_LAPLACE ? 2 : 1;  // axis-0 matrices B (and D)
-    static constexpr int NPL = KronMode<MODE>::NPL;
-    static constexpr int s1f_u16 = NMAT * NPL * K.s1f_elems(), s1b_u16 = NMAT * NPL * K.s1b_elems();
-    static constexpr int s2_u16 = NAM * NPL * 512;
-    static constexpr int off_s1b = 2 * s1f_u16, off_s2 = off_s1b + 2 * s1b_u16, off_w2 = off_s2 + 2 * s2_u16;
-    static constexpr int off_w0 = off_w2 + 4 * 16 * K.NQ;
-    static constexpr int bytes = off_w0 + 4 * 16;
-};
-
 // Workgroup shape and register budget.  Except in the three-term split at n = 5 with
 // FP32 storage, the next tile's u is loaded while the current one computes, and at
 // n = 9 (single term), at n = 5 with FP32 storage (single term) and in the other
@@ -80,79 +66,16 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                         const IO *__restrict__ u, IO *__restrict__ y, const uint16_t *__restrict__ tab,
                         int *__restrict__ err)
 {
-    using SM = K2Smem<N, FORM, MODE>;
-    constexpr Kron2Layout K = SM::K;
-    constexpr int Q2 = K.q2, N3 = N * Q2, CPT = K.cpt, RS = K.rs, NQ = K.NQ, KS = K.KS, NQ2 = K.NQ2;
-    constexpr int NMAT = SM::NMAT, NAM = SM::NAM, NPL = SM::NPL, NPROD = KronMode<MODE>::NPROD;
-    constexpr int PL0 = KronMode<MODE>::PLANE0;
-    __shared__ __align__(16) unsigned char smem[SM::bytes];
-    const uint16_t *const s1f = reinterpret_cast<const uint16_t *>(smem);
-    const uint16_t *const s1b = reinterpret_cast<const uint16_t *>(smem + SM::off_s1b);
-    const uint16_t *const s2 = reinterpret_cast<const uint16_t *>(smem + SM::off_s2);
-    const float *const sW2 = reinterpret_cast<const float *>(smem + SM::off_w2);
-    const float *const sW0 = reinterpret_cast<const float *>(smem + SM::off_w0);
-
-    // ---- tables into LDS, once per workgroup; each thread issues all of its loads of
-    // a section before its stores.  LDS order: s1f [a][plane], s1b [a][plane],
-    // s2 [axis-0 matrix][plane] (s2f then s2b), plane weights, axis-0 weights.
-    {
-        constexpr int W1F = K.s1f_elems() / 8, W1B = K.s1b_elems() / 8; // 16-byte words per block
-        constexpr int T1 = NMAT * NPL * (W1F + W1B), T2 = NAM * NPL * 64, TW = (16 * NQ + 16) / 4;
-        constexpr int TOT = T1 + T2 + TW, R = (TOT + 64 * WAVES - 1) / (64 * WAVES);
-        uint4 v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            int t = int(threadIdx.x) + r * 64 * WAVES;
-            t = t < TOT ? t : TOT - 1;
-            int src; // uint16 offset of the word in the global block
-            if (t < NMAT * NPL * W1F) {
-                const int mp = t / W1F, e = t % W1F;
-                src = K.s1f(mp / NPL, NPL == 1 ? PL0 : mp % NPL) + 8 * e;
-            } else if (t < T1) {
-                const int tt = t - NMAT * NPL * W1F, mp = tt / W1B, e = tt % W1B;
-                src = K.s1b(mp / NPL, NPL == 1 ? PL0 : mp % NPL) + 8 * e;
-            } else if (t < T1 + T2) {
-                const int tt = t - T1, mp = tt / 64, e = tt % 64;
-                src = K.s2f(mp / NPL, NPL == 1 ? PL0 : mp % NPL) + 8 * e;
-            } else {
-                src = K.w2() + 8 * (t - T1 - T2); // w2 and w0 are contiguous
-            }
-            v[r] = *reinterpret_cast<const uint4 *>(tab + src);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int t = int(threadIdx.x) + r * 64 * WAVES;
-            if (t < TOT) reinterpret_cast<uint4 *>(smem)[t] = v[r];
-        }
-    }
+    constexpr int CPT = Kron2Layout(N).cpt;
+    __shared__ __align__(16) unsigned char smem[K2Smem<N, FORM, MODE>::bytes];
+    const auto tabs = Kron2LdsTables<N, FORM, MODE>::at(smem);
+    // ---- tables into LDS, once per workgroup
+    kron2_stage<N, FORM, MODE, 64 * WAVES>(tab, smem);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6;
     // a batch is the cells of 16 / CPT tiles (16, or 15 with three cells per tile)
     constexpr int BATCH = CPT * (16 / CPT);
-    // the LDS copy of the tables: components in order, the mode's terms only
-    struct {
-        const uint16_t *s1f_, *s1b_, *s2_;
-        const float *w2_, *w0_;
-        __device__ __forceinline__ u32x4 s1f(int a, int p, int i) const
-        {
-            return reinterpret_cast<const u32x4 *>(s1f_ + (a * NPL + p) * Kron2Layout(N).s1f_elems())[i];
-        }
-        __device__ __forceinline__ u32x4 s1b(int a, int p, int i) const
-        {
-            return reinterpret_cast<const u32x4 *>(s1b_ + (a * NPL + p) * Kron2Layout(N).s1b_elems())[i];
-        }
-        __device__ __forceinline__ u32x2 s2f(int am, int p, int lane) const
-        {
-            return reinterpret_cast<const u32x2 *>(s2_ + (am * NPL + p) * 512)[lane];
-        }
-        __device__ __forceinline__ u32x2 s2b(int am, int p, int lane) const
-        {
-            return reinterpret_cast<const u32x2 *>(s2_ + (am * NPL + p) * 512 + 256)[lane];
-        }
-        __device__ __forceinline__ float w2(int q) const { return w2_[q]; }
-        __device__ __forceinline__ float w0(int r) const { return w0_[r]; }
-    } const tabs{s1f, s1b, s2, sW2, sW0};
     const int64_t nbatch = (ncells + BATCH - 1) / BATCH;
     for (int64_t bt = int64_t(blockIdx.x) * WAVES + wave; bt < nbatch; bt += int64_t(gridDim.x) * WAVES) {
         kron2_batch<N, FORM, MODE, IO, K2Cfg<N, FORM, MODE, IO>::PF, decltype(tabs), K2Cfg<N, FORM, MODE, IO>::KPF>(bt * BATCH, ncells, tabs, vert, kappa, u, y, err);
