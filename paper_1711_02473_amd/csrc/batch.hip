@@ -74,10 +74,13 @@ struct BatchTile {
 };
 
 // Mixed-precision action tiles run the dense Kronecker bodies except at n = 9 (BF16x3 and
-// single term) where the sum-factorised MFMA body runs: BF16x3 with the tables read from
-// global memory (no LDS: its tables would not fit beside the other classes), the single-term
-// modes with the tables staged in LDS once per tile (at most 51.5 KB, n = 7, 8)
-template <int N, int KIND> constexpr bool kron_lds() { return (KIND == K_ACT_BF16 || KIND == K_ACT_FP16) && N <= 8; }
+// single term) where the sum-factorised MFMA body runs.  The tables are staged in LDS once
+// per tile where they take at most 51.5 KB (below the FP64 classes' 56 KB): the single-term
+// modes, and BF16x3 at n = 3 and 5; the other BF16x3 tiles read them from global memory.
+template <int N, int KIND> constexpr bool kron_lds()
+{
+    return ((KIND == K_ACT_BF16 || KIND == K_ACT_FP16) && N <= 8) || (KIND == K_ACT_BF16X3 && (N == 3 || N == 5));
+}
 template <int N, int KIND> constexpr bool kron_tiles() { return (KIND == K_ACT_BF16X3 && N != 9) || kron_lds<N, KIND>(); }
 
 template <int N> struct Cls {
@@ -91,6 +94,9 @@ template <int N> struct Cls {
     }
     static constexpr int smem(int kind)
     {
+        if (kind == K_ACT_BF16X3 && (N == 3 || N == 5)) // the three-term tables in LDS
+            return N <= 4 ? kron::KronSmem<N, SF_LAPLACE, SF_BF16X3>::bytes
+                          : kron::K2Smem<N, SF_LAPLACE, SF_BF16X3>::bytes;
         if (kind == K_ACT_BF16X3 && N != 9) return 0; // the dense Kronecker bodies, global tables
         if ((kind == K_ACT_BF16 || kind == K_ACT_FP16) && N <= 8) // the tables (BF16 and FP16 planes alike)
             return N <= 4 ? kron::KronSmem<N, SF_LAPLACE, SF_BF16>::bytes : kron::K2Smem<N, SF_LAPLACE, SF_BF16>::bytes;
