@@ -278,7 +278,8 @@ int assemble_element_matrix(sf_context *ctx, const sf_op *op, int64_t ncells, co
 int sf_check_errors(sf_context *ctx, void *hip_stream, int32_t *flags);
 
 /*
- * Global continuous Q_p numbering on an nx*ny*nz tensor grid of cells (cell
+ * Global continuous Q_p numbering on an nx*ny*nz tensor grid of cells (the
+ * assembled operator of Sec. 4.2, whose rates count these global DOFs; cell
  * (i,j,k) is number (i*ny+j)*nz+k): local node (i0,i1,i2) of cell (i,j,k) is
  * the lattice point (a,b,c) = (i*p+i0, j*p+i1, k*p+i2), numbered
  * (a*(ny*p+1)+b)*(nz*p+1)+c.  Written by a GPU kernel into map_device, int32
