@@ -14,9 +14,11 @@ def host(t):
 
 
 def empty(shape, dtype):
+    """An output buffer on the device, pre-filled with NaN (floating point) or -1
+    (integers) so that an entry the library leaves unwritten fails the comparison."""
     import torch
     t = {np.float64: torch.float64, np.float32: torch.float32, np.int32: torch.int32}[dtype]
-    return torch.empty(shape, dtype=t, device="cuda")
+    return torch.full(shape, float("nan") if t.is_floating_point else -1, dtype=t, device="cuda")
 
 
 def rel_l2(x, ref):
