@@ -75,8 +75,9 @@ struct BatchTile {
 
 // Mixed-precision action tiles run the dense Kronecker bodies except at n = 9 (BF16x3 and
 // single term) where the sum-factorised MFMA body runs.  The tables are staged in LDS once
-// per tile where they take at most 51.5 KB (below the FP64 classes' 56 KB): the single-term
-// modes, and BF16x3 at n = 3 and 5; the other BF16x3 tiles read them from global memory.
+// per tile where they take at most 51.5 KB (three workgroups still fit per CU; the FP64
+// classes take up to 56 KB): the single-term modes, and BF16x3 at n = 3 and 5; the other
+// BF16x3 tiles read them from global memory.
 template <int N, int KIND> constexpr bool kron_lds()
 {
     return ((KIND == K_ACT_BF16 || KIND == K_ACT_FP16) && N <= 8) || (KIND == K_ACT_BF16X3 && (N == 3 || N == 5));
