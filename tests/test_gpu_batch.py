@@ -122,7 +122,7 @@ def test_batch_graph_replays_match_standalone_and_oracle(ctx, ctx_box, geom):
     # oracle on a sample of cells of every job
     for r, ref in zip(jobs, refs):
         idx = np.unique(np.linspace(0, r["n"] - 1, 4).astype(int))
-        tol = {"fp64": 1e-12, "bf16x3": 1e-6, "fp16": 2e-2, "bf16": 1.5e-1 if r["kind"] == "act" else 2e-2}[r["prec"]]
+        tol = {"fp64": 1e-12, "bf16x3": 1e-6, "fp16": 1e-2, "bf16": 4e-2 if r["kind"] == "act" else 2e-2}[r["prec"]]
         if r["kind"] == "act":
             o = oracle.action("Q", r["p"], "LAPLACE", r["V"][idx], r["u"][idx], kappa=r["kap"][idx])
             assert rel_l2(ref[idx], o) <= tol

@@ -15,7 +15,11 @@ from tests.gpu_util import dev, empty, host, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-BOUND = {"bf16x3": 1e-6, "fp16": 2e-2, "bf16": 1.5e-1}
+# relative L2 bounds of the actions: BF16x3 the precision target; the single-term modes
+# about 20x their unit roundoff (BF16 2^-9, FP16 2^-11), which covers the four rounded
+# contraction stages, the sum-factorised kernel (two to three times the dense kernels'
+# error) and sheared cells (measured: BF16 2-9e-3, FP16 3-6e-4)
+BOUND = {"bf16x3": 1e-6, "fp16": 1e-2, "bf16": 4e-2}
 
 
 @pytest.fixture(scope="module")
